@@ -1,0 +1,106 @@
+/*
+ * Serial FP64 CPU oracle for the LDU pressure solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow reference that
+ * the GPU library is checked against.  Only the test suite, the smoke check
+ * and the benchmark's CPU-baseline leg may load it; the product path never
+ * calls it.  It shares no code, header or constant table with the GPU path.
+ *
+ * Matrix storage is OpenFOAM's lduMatrix form (paper Sec. 2.1): diag[n] plus,
+ * for each internal face f, upper[f] = A[owner[f], neighbour[f]] and
+ * lower[f] = A[neighbour[f], owner[f]], faces sorted by (owner, neighbour)
+ * with owner < neighbour.
+ *
+ * Parity status of each routine is recorded in the header comment of the
+ * routine in ldu_oracle.c.
+ */
+#ifndef LDU_ORACLE_H
+#define LDU_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_OK 0
+#define ORC_NOT_CONVERGED 1
+#define ORC_ERR_ARG (-1)
+#define ORC_ERR_ADDR (-2)
+#define ORC_ERR_NAN (-3)
+#define ORC_ERR_BREAKDOWN (-4)
+
+/* addressing and value checks */
+int orc_validate(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+                 const double *diag, const double *upper, const double *lower);
+
+/* y = A x and y = A^T x, FP64 */
+void orc_amul(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+              const double *diag, const double *upper, const double *lower,
+              const double *x, double *y);
+void orc_tmul(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+              const double *diag, const double *upper, const double *lower,
+              const double *x, double *y);
+/* y = A x with every value, product and sum in IEEE single precision */
+void orc_amul_f32(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+                  const float *diag, const float *upper, const float *lower,
+                  const float *x, float *y);
+
+/* diagonal- (precond=1) or un-preconditioned (precond=0) CG, FP64.
+ * x holds x0 on entry.  hist (may be NULL) receives ||r_k||/||b|| for
+ * k = 0..iters and must hold max_iter+2 entries.  transpose=1 solves A^T x=b. */
+int orc_pcg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+            const double *diag, const double *upper, const double *lower,
+            const double *b, double *x, double tol, int max_iter, int precond,
+            int transpose, int *iters, double *hist, double *true_res);
+
+/* FP32 inner CG with FP64 iterative refinement (outer loop in FP64) */
+int orc_pcg_mixed(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+                  const double *diag, const double *upper, const double *lower,
+                  const double *b, double *x, double tol, int max_refine,
+                  double inner_tol, int inner_max_iter, int transpose,
+                  int *refinements, int *inner_iters, double *hist,
+                  double *true_res);
+
+/* ---- GAMG: pairwise agglomeration hierarchy, V-cycle, solve ---- */
+typedef struct orc_gamg orc_gamg;
+
+orc_gamg *orc_gamg_build(int32_t n, int64_t nf, const int32_t *own,
+                         const int32_t *nb, const double *diag,
+                         const double *upper, const double *lower,
+                         int n_coarsest, int max_levels, int match_rounds);
+void orc_gamg_free(orc_gamg *h);
+int orc_gamg_nlevels(const orc_gamg *h);
+void orc_gamg_level_size(const orc_gamg *h, int level, int64_t *n, int64_t *nf);
+/* agg may be NULL; it is only defined for levels below the coarsest */
+void orc_gamg_level_export(const orc_gamg *h, int level, int32_t *agg,
+                           int32_t *own, int32_t *nb, double *diag,
+                           double *upper, double *lower);
+/* matching state of one level (partner, leftover join target), for tests */
+void orc_gamg_level_match(const orc_gamg *h, int level, int32_t *partner,
+                          int32_t *join);
+
+/* one V-cycle e = V(0, r) (e is output only) */
+int orc_gamg_vcycle(const orc_gamg *h, const double *r, double *e, int n_pre,
+                    int n_post, double omega, int scale, int transpose);
+int orc_gamg_solve(const orc_gamg *h, const double *b, double *x, double tol,
+                   int max_cycles, int n_pre, int n_post, double omega,
+                   int scale, int transpose, int *cycles, double *hist,
+                   double *true_res);
+/* FP32 V-cycle (coarsest level in FP64) inside FP64 refinement */
+int orc_gamg_mixed(const orc_gamg *h, const double *b, double *x, double tol,
+                   int max_refine, int n_pre, int n_post, double omega,
+                   int scale, int transpose, int *refinements, double *hist,
+                   double *true_res);
+
+/* per-face / per-cell gradients of L(x) with lambda = A^-T dL/dx:
+ * g_diag = -lambda o x, g_upper[f] = -lambda[own] x[nb],
+ * g_lower[f] = -lambda[nb] x[own] */
+void orc_coeff_grad(int32_t n, int64_t nf, const int32_t *own,
+                    const int32_t *nb, const double *lambda, const double *x,
+                    double *g_diag, double *g_upper, double *g_lower);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

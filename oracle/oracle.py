@@ -1,0 +1,278 @@
+"""ctypes binding of the C oracle (test infrastructure only).
+
+Builds oracle/libldu_oracle.so with gcc on first use when it is missing.
+Every function takes and returns numpy arrays; nothing here touches a GPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ldu_oracle.c")
+_LIB = os.path.join(_HERE, "libldu_oracle.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_ARG, ERR_ADDR, ERR_NAN, ERR_BREAKDOWN = -1, -2, -3, -4
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle (plain C, no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+            os.path.getmtime(_SRC),
+            os.path.getmtime(os.path.join(_HERE, "ldu_oracle.h"))):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+             "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+
+
+def _opt(ptr_t):
+    """ndpointer that also accepts None."""
+    class _P(ptr_t):
+        @classmethod
+        def from_param(cls, obj):
+            if obj is None:
+                return None
+            return ptr_t.from_param(obj)
+    return _P
+
+
+_f64o = _opt(_f64p)
+_i32o = _opt(_i32p)
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    L = C.CDLL(build())
+    i32, i64, d, vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    ip = C.POINTER(C.c_int)
+    dp = C.POINTER(C.c_double)
+    L.orc_validate.argtypes = [i32, i64, _i32p, _i32p, _f64o, _f64o, _f64o]
+    L.orc_amul.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p]
+    L.orc_tmul.argtypes = L.orc_amul.argtypes
+    L.orc_amul_f32.argtypes = [i32, i64, _i32p, _i32p, _f32p, _f32p, _f32p, _f32p, _f32p]
+    L.orc_pcg.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p,
+                          d, C.c_int, C.c_int, C.c_int, ip, _f64o, dp]
+    L.orc_pcg_mixed.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p,
+                                _f64p, d, C.c_int, d, C.c_int, C.c_int, ip, ip, _f64o, dp]
+    L.orc_gamg_build.restype = vp
+    L.orc_gamg_build.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p,
+                                 C.c_int, C.c_int, C.c_int]
+    L.orc_gamg_free.argtypes = [vp]
+    L.orc_gamg_nlevels.argtypes = [vp]
+    L.orc_gamg_level_size.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(i64)]
+    L.orc_gamg_level_export.argtypes = [vp, C.c_int, _i32o, _i32o, _i32o, _f64o,
+                                        _f64o, _f64o]
+    L.orc_gamg_level_match.argtypes = [vp, C.c_int, _i32o, _i32o]
+    L.orc_gamg_vcycle.argtypes = [vp, _f64p, _f64p, C.c_int, C.c_int, d, C.c_int,
+                                  C.c_int]
+    L.orc_gamg_solve.argtypes = [vp, _f64p, _f64p, d, C.c_int, C.c_int, C.c_int, d,
+                                 C.c_int, C.c_int, ip, _f64o, dp]
+    L.orc_gamg_mixed.argtypes = [vp, _f64p, _f64p, d, C.c_int, C.c_int, C.c_int, d,
+                                 C.c_int, C.c_int, ip, _f64o, dp]
+    L.orc_coeff_grad.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p,
+                                 _f64p, _f64p]
+    _lib = L
+    return L
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Ldu:
+    """An LDU matrix as held by the oracle (plain numpy arrays)."""
+
+    def __init__(self, n, owner, neighbour, diag, upper, lower):
+        self.n = int(n)
+        self.own = _c(owner, np.int32)
+        self.nb = _c(neighbour, np.int32)
+        self.diag = _c(diag, np.float64)
+        self.upper = _c(upper, np.float64)
+        self.lower = _c(lower, np.float64)
+        self.nf = int(self.own.shape[0])
+
+    @classmethod
+    def from_case(cls, case):
+        return cls(case.n_cells, case.owner, case.neighbour, case.diag,
+                   case.upper, case.lower)
+
+    def args(self):
+        return (self.n, self.nf, self.own, self.nb, self.diag, self.upper,
+                self.lower)
+
+
+def validate(n, owner, neighbour, diag=None, upper=None, lower=None):
+    return lib().orc_validate(
+        int(n), int(len(owner)), _c(owner, np.int32), _c(neighbour, np.int32),
+        None if diag is None else _c(diag, np.float64),
+        None if upper is None else _c(upper, np.float64),
+        None if lower is None else _c(lower, np.float64))
+
+
+def amul(A: Ldu, x):
+    y = np.empty(A.n)
+    lib().orc_amul(*A.args(), _c(x, np.float64), y)
+    return y
+
+
+def tmul(A: Ldu, x):
+    y = np.empty(A.n)
+    lib().orc_tmul(*A.args(), _c(x, np.float64), y)
+    return y
+
+
+def amul_f32(A: Ldu, x):
+    y = np.empty(A.n, np.float32)
+    lib().orc_amul_f32(A.n, A.nf, A.own, A.nb, A.diag.astype(np.float32),
+                       A.upper.astype(np.float32), A.lower.astype(np.float32),
+                       _c(x, np.float32), y)
+    return y
+
+
+@dataclass
+class SolveResult:
+    status: int
+    x: np.ndarray
+    iterations: int
+    history: np.ndarray
+    true_residual: float
+    inner_iterations: int = 0
+
+
+def pcg(A: Ldu, b, x0=None, tol=1e-8, max_iter=10000, precond=True,
+        transpose=False):
+    x = np.zeros(A.n) if x0 is None else _c(x0, np.float64).copy()
+    hist = np.zeros(max_iter + 2)
+    it = C.c_int(0)
+    tr = C.c_double(0.0)
+    st = lib().orc_pcg(*A.args(), _c(b, np.float64), x, float(tol),
+                       int(max_iter), int(bool(precond)), int(bool(transpose)),
+                       C.byref(it), hist, C.byref(tr))
+    return SolveResult(st, x, it.value, hist[: it.value + 1].copy(), tr.value)
+
+
+def pcg_mixed(A: Ldu, b, x0=None, tol=1e-8, max_refine=50, inner_tol=1e-4,
+              inner_max_iter=1000, transpose=False):
+    x = np.zeros(A.n) if x0 is None else _c(x0, np.float64).copy()
+    hist = np.zeros(max_refine + 2)
+    k = C.c_int(0)
+    inner = C.c_int(0)
+    tr = C.c_double(0.0)
+    st = lib().orc_pcg_mixed(*A.args(), _c(b, np.float64), x, float(tol),
+                             int(max_refine), float(inner_tol),
+                             int(inner_max_iter), int(bool(transpose)),
+                             C.byref(k), C.byref(inner), hist, C.byref(tr))
+    return SolveResult(st, x, k.value, hist[: k.value + 1].copy(), tr.value,
+                       inner.value)
+
+
+@dataclass
+class Level:
+    n: int
+    nf: int
+    agg: np.ndarray | None
+    owner: np.ndarray
+    neighbour: np.ndarray
+    diag: np.ndarray
+    upper: np.ndarray
+    lower: np.ndarray
+    partner: np.ndarray | None = None
+    join: np.ndarray | None = None
+
+
+class Gamg:
+    """Oracle GAMG hierarchy (built once; values and structure fixed)."""
+
+    def __init__(self, A: Ldu, n_coarsest=50, max_levels=50, match_rounds=16):
+        self.A = A
+        self._h = lib().orc_gamg_build(*A.args(), int(n_coarsest),
+                                       int(max_levels), int(match_rounds))
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _lib is not None:
+            _lib.orc_gamg_free(h)
+
+    @property
+    def n_levels(self):
+        return lib().orc_gamg_nlevels(self._h)
+
+    def level(self, l) -> Level:
+        n = C.c_int64()
+        nf = C.c_int64()
+        lib().orc_gamg_level_size(self._h, l, C.byref(n), C.byref(nf))
+        n, nf = n.value, nf.value
+        coarsest = l == self.n_levels - 1
+        agg = None if coarsest else np.empty(n, np.int32)
+        own = np.empty(nf, np.int32)
+        nb = np.empty(nf, np.int32)
+        d = np.empty(n)
+        u = np.empty(nf)
+        lo = np.empty(nf)
+        lib().orc_gamg_level_export(self._h, l, agg, own, nb, d, u, lo)
+        partner = join = None
+        if not coarsest:
+            partner = np.empty(n, np.int32)
+            join = np.empty(n, np.int32)
+            lib().orc_gamg_level_match(self._h, l, partner, join)
+        return Level(n, nf, agg, own, nb, d, u, lo, partner, join)
+
+    def vcycle(self, r, n_pre=2, n_post=2, omega=0.75, scale=True,
+               transpose=False):
+        e = np.zeros(self.A.n)
+        lib().orc_gamg_vcycle(self._h, _c(r, np.float64), e, int(n_pre),
+                              int(n_post), float(omega), int(bool(scale)),
+                              int(bool(transpose)))
+        return e
+
+    def solve(self, b, x0=None, tol=1e-8, max_cycles=200, n_pre=2, n_post=2,
+              omega=0.75, scale=True, transpose=False):
+        x = np.zeros(self.A.n) if x0 is None else _c(x0, np.float64).copy()
+        hist = np.zeros(max_cycles + 2)
+        k = C.c_int(0)
+        tr = C.c_double(0.0)
+        st = lib().orc_gamg_solve(self._h, _c(b, np.float64), x, float(tol),
+                                  int(max_cycles), int(n_pre), int(n_post),
+                                  float(omega), int(bool(scale)),
+                                  int(bool(transpose)), C.byref(k), hist,
+                                  C.byref(tr))
+        return SolveResult(st, x, k.value, hist[: k.value + 1].copy(), tr.value)
+
+    def solve_mixed(self, b, x0=None, tol=1e-8, max_refine=200, n_pre=2,
+                    n_post=2, omega=0.75, scale=True, transpose=False):
+        x = np.zeros(self.A.n) if x0 is None else _c(x0, np.float64).copy()
+        hist = np.zeros(max_refine + 2)
+        k = C.c_int(0)
+        tr = C.c_double(0.0)
+        st = lib().orc_gamg_mixed(self._h, _c(b, np.float64), x, float(tol),
+                                  int(max_refine), int(n_pre), int(n_post),
+                                  float(omega), int(bool(scale)),
+                                  int(bool(transpose)), C.byref(k), hist,
+                                  C.byref(tr))
+        return SolveResult(st, x, k.value, hist[: k.value + 1].copy(), tr.value)
+
+
+def coeff_grad(A: Ldu, lam, x):
+    gd = np.empty(A.n)
+    gu = np.empty(A.nf)
+    gl = np.empty(A.nf)
+    lib().orc_coeff_grad(A.n, A.nf, A.own, A.nb, _c(lam, np.float64),
+                         _c(x, np.float64), gd, gu, gl)
+    return gd, gu, gl

@@ -1,0 +1,81 @@
+"""Dense numpy helpers for pinning the oracle on tiny meshes.
+
+Built straight from the LDU definition A[own,nb] = upper, A[nb,own] = lower,
+A[i,i] = diag (paper Sec. 2.1), independently of the oracle's face loops.
+"""
+import numpy as np
+
+
+def dense(n, owner, neighbour, diag, upper, lower):
+    A = np.zeros((n, n))
+    A[np.arange(n), np.arange(n)] = diag
+    A[owner, neighbour] = upper
+    A[neighbour, owner] = lower
+    return A
+
+
+def dense_case(case):
+    return dense(case.n_cells, case.owner, case.neighbour, case.diag,
+                 case.upper, case.lower)
+
+
+def prolongation(agg, nc):
+    P = np.zeros((agg.size, nc))
+    P[np.arange(agg.size), agg] = 1.0
+    return P
+
+
+def splitmix64_out(z):
+    """SplitMix64 output function (Steele, Lea & Flood 2014), Python ints."""
+    m = (1 << 64) - 1
+    z = (z + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def tie_key(i, j):
+    lo, hi = (i, j) if i < j else (j, i)
+    return splitmix64_out((lo << 32) | hi)
+
+
+def greedy_matching(n, owner, neighbour, upper, lower):
+    """Sequential greedy matching: scan edges by (weight, tie key) descending
+    and take an edge when both ends are free.  With a strict total order on
+    edges this is the unique fixed point of repeated locally-dominant
+    (handshake) matching rounds."""
+    w = 0.5 * (np.abs(upper) + np.abs(lower))
+    keys = [(-w[f], -tie_key(int(owner[f]), int(neighbour[f])), f)
+            for f in range(owner.size)]
+    keys.sort()
+    partner = -np.ones(n, np.int64)
+    for _, _, f in keys:
+        i, j = int(owner[f]), int(neighbour[f])
+        if partner[i] < 0 and partner[j] < 0:
+            partner[i] = j
+            partner[j] = i
+    return partner
+
+
+def closed_form_1d(n, h, kind):
+    """Eigenpairs of the 1D three-point operator -(u_{i-1} - 2u_i + u_{i+1})/h^2.
+
+    kind "neumann": zero gradient at both ends.
+    kind "dirichlet0": half-cell Dirichlet at the left end (boundary
+    coefficient 2/h^2), zero gradient at the right end.
+    kind "dirichlet_node": u_{-1} = u_n = 0 (constant diagonal 2/h^2).
+    Returns (lam [n], V [n, n]) with the k-th eigenvector in column k."""
+    i = np.arange(n)
+    k = np.arange(n)
+    if kind == "neumann":
+        lam = (2 - 2 * np.cos(k * np.pi / n)) / h ** 2
+        V = np.cos(np.outer(i + 0.5, k) * np.pi / n)
+    elif kind == "dirichlet0":
+        lam = (2 - 2 * np.cos((k + 0.5) * np.pi / n)) / h ** 2
+        V = np.sin(np.outer(i + 0.5, k + 0.5) * np.pi / n)
+    elif kind == "dirichlet_node":
+        lam = (2 - 2 * np.cos((k + 1) * np.pi / (n + 1))) / h ** 2
+        V = np.sin(np.outer(i + 1, k + 1) * np.pi / (n + 1))
+    else:
+        raise ValueError(kind)
+    return lam, V

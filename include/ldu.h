@@ -1,0 +1,204 @@
+/*
+ * ldu.h -- C ABI of the MI355X (gfx950) LDU pressure-solve library.
+ *
+ * The library solves A x = b for one scalar matrix stored in OpenFOAM's
+ * lduMatrix form (paper Sec. 2.1, "Design aspects"): a diagonal per cell and,
+ * per internal face f, an upper coefficient A[owner[f], neighbour[f]] and a
+ * lower coefficient A[neighbour[f], owner[f]].  It provides the product
+ * y = A x and its transpose (the "Amul" and "Tmul" SpMVM kernels of the
+ * profiling table, Sec. 4.3), conjugate gradients with the diagonal
+ * preconditioner and the GAMG solver with the Richardson (damped Jacobi)
+ * smoother and a diagonal-PCG coarsest level (the pressure solvers of
+ * Appendix A and of the smoother table in Sec. 4.3), an FP32-bulk variant
+ * with FP64 iterative refinement, and the adjoint solve with per-face
+ * coefficient gradients.
+ *
+ * Conventions shared by every call:
+ *  - Array arguments are DEVICE pointers (HIP device memory of the current
+ *    device), borrowed for the duration of the call only.  The library never
+ *    frees or retains them.  Counts are in elements.
+ *  - hip_stream is a hipStream_t (NULL = the legacy default stream).  All
+ *    device work of a call is ordered on that stream.  Calls that return a
+ *    solver status synchronise that stream before returning.
+ *  - A handle owns all device memory it allocates; allocation happens in
+ *    ldu_create, gamg_setup and the first call of a solver variant, never
+ *    inside an iteration.  A handle is not thread-safe and must be used from
+ *    one stream at a time.
+ *  - Return values: LDU_OK (0) or LDU_NOT_CONVERGED (1, result usable, stats
+ *    filled) or a negative error.  After a negative return, output arrays are
+ *    unspecified and ldu_last_error() describes the failure.  After
+ *    LDU_ERR_HIP the handle is poisoned and later calls return LDU_ERR_STATE.
+ *  - Residuals are ||b - A x||_2 / ||b||_2, computed in FP64 on the device.
+ *    b = 0 yields x = 0 with zero iterations.
+ */
+#ifndef LDU_H
+#define LDU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LDU_ABI_VERSION 1
+
+enum {
+    LDU_OK = 0,
+    LDU_NOT_CONVERGED = 1,
+    LDU_ERR_ARG = -1,       /* bad argument (null pointer, size, option) */
+    LDU_ERR_ADDR = -2,      /* face addressing violates the LDU contract */
+    LDU_ERR_NAN = -3,       /* non-finite coefficient, rhs or residual */
+    LDU_ERR_BREAKDOWN = -4, /* CG breakdown: |p.Ap| <= 1e-300 */
+    LDU_ERR_NOMEM = -5,     /* device allocation failed */
+    LDU_ERR_HIP = -6,       /* HIP runtime error; handle poisoned */
+    LDU_ERR_STATE = -7,     /* poisoned handle or call out of order */
+    LDU_ERR_LIMIT = -8      /* a structural limit of the library was hit */
+};
+
+enum { LDU_FP64 = 0, LDU_MIXED = 1 };
+
+typedef struct ldu_t *ldu_handle;
+
+/* Options of pcg_solve.  Defaults (ldu_pcg_default_opts): rel_tol 1e-8,
+ * abs_tol 0, max_iter 10000, check_every 16, precond 1 (diagonal),
+ * precision LDU_FP64, max_refine 50, inner_rel_tol 1e-4,
+ * inner_max_iter 1000. */
+typedef struct {
+    double rel_tol;       /* stop at ||r||/||b|| <= rel_tol */
+    double abs_tol;       /* unused, reserved: must be 0 */
+    int max_iter;         /* FP64: CG iterations; MIXED: per inner solve cap is inner_max_iter */
+    int check_every;      /* host reads the convergence flag every k iterations (>= 1) */
+    int precond;          /* 0 none, 1 diagonal, 2 one GAMG V-cycle (FP64 only; the
+                             handle's hierarchy and sweep settings from gamg_setup, or
+                             the defaults; correction scaling off so that the
+                             preconditioner is symmetric) */
+    int precision;        /* LDU_FP64 or LDU_MIXED */
+    int max_refine;       /* MIXED: outer refinement steps */
+    int inner_max_iter;   /* MIXED: FP32 CG iterations per refinement */
+    double inner_rel_tol; /* MIXED: inner stop at ||r32||/||rhat|| <= this */
+} ldu_pcg_opts;
+
+/* Options of gamg_setup / gamg_solve.  Defaults (ldu_gamg_default_opts):
+ * rel_tol 1e-8, max_cycles 200, n_coarsest 50, n_pre 2, n_post 2,
+ * max_levels 50, scale_correction 1, match_rounds 16, precision LDU_FP64,
+ * max_refine 200, omega 0.75. */
+typedef struct {
+    double rel_tol;
+    double abs_tol;        /* unused, reserved: must be 0 */
+    int max_cycles;        /* FP64: V-cycles; MIXED: see max_refine */
+    int n_coarsest;        /* coarsen while a level has more cells than this */
+    int n_pre, n_post;     /* Jacobi sweeps before / after the coarse correction */
+    int max_levels;        /* including the finest level, <= 64 */
+    int scale_correction;  /* 1: scale the prolonged correction (energy optimal) */
+    int match_rounds;      /* handshake matching rounds per level */
+    int precision;         /* LDU_FP64 or LDU_MIXED */
+    int max_refine;        /* MIXED: refinement steps (one FP32 V-cycle each) */
+    double omega;          /* Jacobi relaxation factor */
+} ldu_gamg_opts;
+
+typedef struct {
+    int iterations;        /* CG iterations, V-cycles, or (MIXED) inner CG iterations */
+    int refinements;       /* MIXED: outer refinement steps; FP64: 0 */
+    int converged;         /* 1 if the final true residual meets rel_tol */
+    int n_levels;          /* GAMG levels (0 for PCG) */
+    double initial_residual; /* ||b - A x0|| / ||b|| */
+    double final_residual;   /* ||b - A x|| / ||b|| recomputed in FP64 */
+    long long level_cells[64];
+    long long level_faces[64];
+    double *history;       /* optional HOST buffer for the residual history */
+    int history_len;       /* its capacity (entries) */
+    int history_count;     /* entries written */
+} ldu_stats;
+
+void ldu_pcg_default_opts(ldu_pcg_opts *o);
+void ldu_gamg_default_opts(ldu_gamg_opts *o);
+
+/* Create a matrix handle from LDU arrays (Sec. 2.1).
+ * owner, neighbour: int32[nFaces] with 0 <= owner[f] < neighbour[f] < nCells,
+ *   sorted by (owner, neighbour), no duplicates (OpenFOAM's upper-triangular
+ *   face order); otherwise LDU_ERR_ADDR.
+ * diag: double[nCells]; upper, lower: double[nFaces]; non-finite -> LDU_ERR_NAN.
+ * The arrays are copied; the matrix is re-laid on the device into row
+ * segments (the LDU -> row-ordered conversion map of Sec. 3.4) for the
+ * product kernels.  nCells >= 1, nFaces >= 0, 2*nFaces + padding < 2^31. */
+int ldu_create(int32_t nCells, int64_t nFaces, const int32_t *owner,
+               const int32_t *neighbour, const double *diag,
+               const double *upper, const double *lower, void *hip_stream,
+               ldu_handle *out);
+
+/* Replace the coefficients, keeping the addressing.  A GAMG hierarchy that
+ * was set up keeps its agglomeration and recomputes its coarse matrices
+ * (agglomeration caching, Sec. 2.1 and Sec. 4.4). */
+int ldu_set_coeffs(ldu_handle h, const double *diag, const double *upper,
+                   const double *lower, void *hip_stream);
+
+int ldu_destroy(ldu_handle h);
+
+/* y = A x  (Amul), FP64; x, y: double[nCells], must not alias. */
+int ldu_amul(ldu_handle h, const double *x, double *y, void *hip_stream);
+/* y = A^T x  (Tmul): upper and lower exchanged. */
+int ldu_tmul(ldu_handle h, const double *x, double *y, void *hip_stream);
+/* y = A x with FP32 values (rounded from the FP64 coefficients), FP32
+ * vectors and FP32 accumulation. */
+int ldu_amul_f32(ldu_handle h, const float *x, float *y, void *hip_stream);
+
+/* ||b - A x||_2 / ||b||_2 in FP64 (0 when b = 0); *out is a HOST double. */
+int ldu_residual(ldu_handle h, const double *b, const double *x, double *out,
+                 void *hip_stream);
+
+/* Conjugate gradients for A x = b, A symmetric definite (either sign), with
+ * the diagonal preconditioner (Appendix A, "PCG / diagonal") or a GAMG
+ * V-cycle preconditioner (the PCG + AMG pairing of the paper's AmgX
+ * configuration, Appendix A listing).  x: in = initial guess, out = solution.
+ * opts may be NULL (defaults); stats may be NULL.  precision LDU_MIXED runs
+ * FP32 inner CG solves inside FP64 refinement.  Exceeding the iteration
+ * budget returns LDU_NOT_CONVERGED with the last iterate. */
+int pcg_solve(ldu_handle h, const double *b, double *x,
+              const ldu_pcg_opts *opts, ldu_stats *stats, void *hip_stream);
+
+/* Build the GAMG hierarchy (agglomeration + Galerkin coarse matrices); done
+ * lazily by gamg_solve otherwise.  Calling it again rebuilds. */
+int gamg_setup(ldu_handle h, const ldu_gamg_opts *opts, void *hip_stream);
+
+/* GAMG as a solver: per cycle, r = b - A x in FP64 and x += V(r).
+ * precision LDU_MIXED: FP32 V-cycles (FP64 coarsest) inside FP64 refinement. */
+int gamg_solve(ldu_handle h, const double *b, double *x,
+               const ldu_gamg_opts *opts, ldu_stats *stats, void *hip_stream);
+
+/* One V-cycle e = V(r) from e = 0 (FP64); e, r: double[nCells]. */
+int gamg_vcycle(ldu_handle h, const double *r, double *e,
+                const ldu_gamg_opts *opts, void *hip_stream);
+
+/* GAMG hierarchy inspection (for tests and tools).
+ * gamg_level_size: cells and faces of level l (HOST outputs).
+ * gamg_level_export: DEVICE outputs, any may be NULL: agg int32[n_l]
+ *   (coarse cell of each cell; not defined on the coarsest level), owner,
+ *   neighbour int32[nf_l], diag double[n_l], upper, lower double[nf_l]. */
+int gamg_level_size(ldu_handle h, int level, int64_t *n_cells,
+                    int64_t *n_faces);
+int gamg_level_export(ldu_handle h, int level, int32_t *agg, int32_t *owner,
+                      int32_t *neighbour, double *diag, double *upper,
+                      double *lower, void *hip_stream);
+
+/* Adjoint solve A^T lambda = g with PCG (use_gamg = 0, opts is an
+ * ldu_pcg_opts*) or GAMG (use_gamg = 1, opts is an ldu_gamg_opts*), on the
+ * transposed coefficients (upper and lower exchanged on every level). */
+int ldu_adjoint_solve(ldu_handle h, const double *g, double *lambda,
+                      int use_gamg, const void *opts, ldu_stats *stats,
+                      void *hip_stream);
+
+/* Gradients of a loss L through A x = b given lambda = A^-T dL/dx:
+ * g_diag[i] = -lambda[i] x[i], g_upper[f] = -lambda[owner[f]] x[neighbour[f]],
+ * g_lower[f] = -lambda[neighbour[f]] x[owner[f]] (and dL/db = lambda).
+ * Outputs in the caller's face order; any output may be NULL. */
+int ldu_coeff_grad(ldu_handle h, const double *lambda, const double *x,
+                   double *g_diag, double *g_upper, double *g_lower,
+                   void *hip_stream);
+
+/* Description of the last error on the calling thread. */
+const char *ldu_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -275,25 +275,26 @@ def c3_spacing(n=200):
     return dx, dz
 
 
-def config_c3(n=200) -> LduCase:
+def config_c3(n=200, nxy=None) -> LduCase:
     """200^3 graded FV hex mesh: dx = dy = 1/n, dz_k = min((dx/100) 1.05^k, dx)
     (aspect ratio up to 100); FV coefficients a_x = a_y = dz_k,
     a_z = dx^2 / ((dz_k + dz_k+1)/2), times U[0.95, 1.05] per face; Dirichlet
     at the top layer with a_b = dx^2/(dz_top/2); zero gradient elsewhere;
     rhs ~ N(0,1)."""
     dx, dz = c3_spacing(n)
-    own, nb, ax = box_faces(n, n, n)
-    N = n ** 3
-    kz = own // (n * n)
+    m = n if nxy is None else nxy  # nxy < n: same z grading on a narrower box
+    own, nb, ax = box_faces(m, m, n)
+    N = m * m * n
+    kz = own // (m * m)
     a = np.where(ax < 2, dz[kz],
                  dx * dx / (0.5 * (dz[kz] + dz[np.minimum(kz + 1, n - 1)])))
     a = a * _rng(3, 2).uniform(0.95, 1.05, own.size)
     ab = np.zeros(N)
-    ab[np.arange(N) // (n * n) == n - 1] = dx * dx / (0.5 * dz[n - 1])
+    ab[np.arange(N) // (m * m) == n - 1] = dx * dx / (0.5 * dz[n - 1])
     diag = assemble_diag(N, own, nb, a, a, ab)
     b = _rng(3, 3).standard_normal(N)
     return LduCase("c3", N, own, nb, diag, a, a.copy(), [b], False,
-                   {"shape": (n, n, n)})
+                   {"shape": (m, m, n)})
 
 
 def config_c4(n=256, order="rcm") -> LduCase:

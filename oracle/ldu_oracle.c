@@ -148,14 +148,26 @@ typedef struct {
     double *r, *z, *p, *q;
 } cg_work;
 
+/* preconditioner z = M^-1 r: 0 identity, 1 diagonal, or a callback */
+typedef void (*precond_fn)(void *ctx, const double *r, double *z);
+
+static void apply_precond(const omat *m, int precond, precond_fn fn, void *ctx,
+                          const double *r, double *z) {
+    if (fn) {
+        fn(ctx, r, z);
+        return;
+    }
+    for (int32_t i = 0; i < m->n; ++i) z[i] = precond ? r[i] / m->diag[i] : r[i];
+}
+
 /* one CG run from the residual already in w->r; returns ORC_OK when the
  * recursive residual reached tol, ORC_NOT_CONVERGED when *total hit max_iter */
-static int cg_run(const omat *m, int precond, double *x, cg_work *w,
-                  double bnorm, double tol, int max_iter, int *total,
-                  double *hist) {
+static int cg_run_pc(const omat *m, int precond, precond_fn fn, void *ctx,
+                     double *x, cg_work *w, double bnorm, double tol,
+                     int max_iter, int *total, double *hist) {
     const int32_t n = m->n;
     double *r = w->r, *z = w->z, *p = w->p, *q = w->q;
-    for (int32_t i = 0; i < n; ++i) z[i] = precond ? r[i] / m->diag[i] : r[i];
+    apply_precond(m, precond, fn, ctx, r, z);
     for (int32_t i = 0; i < n; ++i) p[i] = z[i];
     double rho = dot(n, r, z);
     while (*total < max_iter) {
@@ -170,7 +182,7 @@ static int cg_run(const omat *m, int precond, double *x, cg_work *w,
         if (hist) hist[*total] = res;
         if (!isfinite(res)) return ORC_ERR_NAN;
         if (res <= tol) return ORC_OK;
-        for (int32_t i = 0; i < n; ++i) z[i] = precond ? r[i] / m->diag[i] : r[i];
+        apply_precond(m, precond, fn, ctx, r, z);
         double rho_new = dot(n, r, z);
         double beta = rho_new / rho;
         rho = rho_new;
@@ -179,11 +191,19 @@ static int cg_run(const omat *m, int precond, double *x, cg_work *w,
     return ORC_NOT_CONVERGED;
 }
 
-int orc_pcg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
-            const double *diag, const double *upper, const double *lower,
-            const double *b, double *x, double tol, int max_iter, int precond,
-            int transpose, int *iters, double *hist, double *true_res) {
-    omat m = make_mat(n, nf, own, nb, diag, upper, lower, transpose);
+static int cg_run(const omat *m, int precond, double *x, cg_work *w,
+                  double bnorm, double tol, int max_iter, int *total,
+                  double *hist) {
+    return cg_run_pc(m, precond, NULL, NULL, x, w, bnorm, tol, max_iter, total,
+                     hist);
+}
+
+/* CG driver with restarts from the true residual (shared by every
+ * preconditioner) */
+static int cg_solve(const omat *m, int precond, precond_fn fn, void *ctx,
+                    const double *b, double *x, double tol, int max_iter,
+                    int *iters, double *hist, double *true_res) {
+    const int32_t n = m->n;
     int total = 0;
     double bnorm = sqrt(dot(n, b, b));
     if (iters) *iters = 0;
@@ -198,7 +218,7 @@ int orc_pcg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
     w.z = xcalloc(n, sizeof(double));
     w.p = xcalloc(n, sizeof(double));
     w.q = xcalloc(n, sizeof(double));
-    residual(&m, b, x, w.r);
+    residual(m, b, x, w.r);
     double res = sqrt(dot(n, w.r, w.r)) / bnorm;
     if (hist) hist[0] = res;
     int st = ORC_OK;
@@ -206,9 +226,10 @@ int orc_pcg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
         st = ORC_ERR_NAN;
     } else {
         while (res > tol) {
-            st = cg_run(&m, precond, x, &w, bnorm, tol, max_iter, &total, hist);
+            st = cg_run_pc(m, precond, fn, ctx, x, &w, bnorm, tol, max_iter,
+                           &total, hist);
             if (st < 0) break;
-            residual(&m, b, x, w.r); /* true residual, restart point */
+            residual(m, b, x, w.r); /* true residual, restart point */
             res = sqrt(dot(n, w.r, w.r)) / bnorm;
             if (res <= tol) { st = ORC_OK; break; }
             if (total >= max_iter) { st = ORC_NOT_CONVERGED; break; }
@@ -218,6 +239,15 @@ int orc_pcg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
     if (true_res) *true_res = res;
     free(w.r); free(w.z); free(w.p); free(w.q);
     return st;
+}
+
+int orc_pcg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+            const double *diag, const double *upper, const double *lower,
+            const double *b, double *x, double tol, int max_iter, int precond,
+            int transpose, int *iters, double *hist, double *true_res) {
+    omat m = make_mat(n, nf, own, nb, diag, upper, lower, transpose);
+    return cg_solve(&m, precond, NULL, NULL, b, x, tol, max_iter, iters, hist,
+                    true_res);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -377,7 +407,8 @@ int orc_pcg_mixed(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
 /* Vcycle).  The paper keeps OpenFOAM's serial coarsening and does not state */
 /* it; this oracle uses a parallel-friendly pairwise matching, defined as:   */
 /*                                                                            */
-/*  weight of face f:  w_f = 0.5*(|upper_f| + |lower_f|)                      */
+/*  weight of face f between i and j: the squared diagonally scaled strength  */
+/*  w_f = (0.5*(|upper_f| + |lower_f|))^2 / |diag_i diag_j|                    */
 /*  order of candidate neighbours j of cell i: larger w first, then larger    */
 /*  tie key h(min(i,j), max(i,j)) (SplitMix64 output function of the packed   */
 /*  pair, Steele, Lea & Flood 2014), then smaller j.                          */
@@ -432,6 +463,16 @@ static uint64_t tie_key(int32_t i, int32_t j) {
     return splitmix64_out((lo << 32) | hi);
 }
 
+/* squared strength of the coupling between cells i and j through face f:
+ * (|upper_f| + |lower_f|)^2 / 4 divided by |diag_i diag_j| (the coupling
+ * relative to the diagonals; no square root, so it rounds identically
+ * everywhere).  A zero diagonal product falls back to the unscaled value. */
+static double strength2(double up, double lo, double di, double dj) {
+    double s = 0.5 * (fabs(up) + fabs(lo));
+    double den = fabs(di) * fabs(dj);
+    return den > 0.0 ? (s * s) / den : s * s;
+}
+
 /* is candidate (w1,h1,j1) better than (w2,h2,j2)? */
 static int better(double w1, uint64_t h1, int32_t j1, double w2, uint64_t h2,
                   int32_t j2) {
@@ -484,7 +525,7 @@ static int32_t best_neighbour(const olevel *L, const adjacency *a, int32_t i,
         int unmatched = partner[j] < 0;
         if (unmatched != want_unmatched) continue;
         int64_t f = a->face[k];
-        double w = 0.5 * (fabs(L->up[f]) + fabs(L->lo[f]));
+        double w = strength2(L->up[f], L->lo[f], L->diag[i], L->diag[j]);
         uint64_t h = tie_key(i, j);
         if (best < 0 || better(w, h, j, bw, bh, best)) {
             best = j;
@@ -608,6 +649,18 @@ static void level_f32(olevel *L) {
     }
 }
 
+/* singular coarsest level: every row sum of A is zero to rounding */
+static void set_singular(olevel *C) {
+    double *one = xcalloc((size_t)C->n, sizeof(double));
+    double *y = xcalloc((size_t)C->n, sizeof(double));
+    for (int32_t i = 0; i < C->n; ++i) one[i] = 1.0;
+    orc_amul(C->n, C->nf, C->own, C->nb, C->diag, C->up, C->lo, one, y);
+    C->singular = C->n > 0;
+    for (int32_t i = 0; i < C->n; ++i)
+        if (!(fabs(y[i]) <= 1e-12 * fabs(C->diag[i]))) C->singular = 0;
+    free(one); free(y);
+}
+
 orc_gamg *orc_gamg_build(int32_t n, int64_t nf, const int32_t *own,
                          const int32_t *nb, const double *diag,
                          const double *upper, const double *lower,
@@ -642,17 +695,30 @@ orc_gamg *orc_gamg_build(int32_t n, int64_t nf, const int32_t *own,
         h->nlev++;
     }
     for (int l = 0; l < h->nlev; ++l) level_f32(&h->lev[l]);
-    /* singular coarsest level: every row sum of A is zero to rounding */
-    olevel *C = &h->lev[h->nlev - 1];
-    double *one = xcalloc((size_t)C->n, sizeof(double));
-    double *y = xcalloc((size_t)C->n, sizeof(double));
-    for (int32_t i = 0; i < C->n; ++i) one[i] = 1.0;
-    orc_amul(C->n, C->nf, C->own, C->nb, C->diag, C->up, C->lo, one, y);
-    C->singular = C->n > 0;
-    for (int32_t i = 0; i < C->n; ++i)
-        if (!(fabs(y[i]) <= 1e-12 * fabs(C->diag[i]))) C->singular = 0;
-    free(one); free(y);
+    set_singular(&h->lev[h->nlev - 1]);
     return h;
+}
+
+/* new fine-level coefficients on a cached hierarchy: the aggregation of
+ * every level is kept and each coarse matrix is recomputed by the Galerkin
+ * product (OpenFOAM's cached GAMG agglomeration) */
+void orc_gamg_set_values(orc_gamg *h, const double *diag, const double *upper,
+                         const double *lower) {
+    olevel *L0 = &h->lev[0];
+    memcpy(L0->diag, diag, (size_t)L0->n * sizeof(double));
+    memcpy(L0->up, upper, (size_t)L0->nf * sizeof(double));
+    memcpy(L0->lo, lower, (size_t)L0->nf * sizeof(double));
+    for (int l = 0; l + 1 < h->nlev; ++l) {
+        olevel *F = &h->lev[l], *C = &h->lev[l + 1];
+        free(C->own); free(C->nb); free(C->diag); free(C->up); free(C->lo);
+        galerkin(F, C->n, C);
+    }
+    for (int l = 0; l < h->nlev; ++l) {
+        olevel *L = &h->lev[l];
+        free(L->diag32); free(L->up32); free(L->lo32);
+        level_f32(L);
+    }
+    set_singular(&h->lev[h->nlev - 1]);
 }
 
 void orc_gamg_free(orc_gamg *h) {
@@ -828,6 +894,30 @@ int orc_gamg_solve(const orc_gamg *h, const double *b, double *x, double tol,
     if (true_res) *true_res = res;
     free(r); free(e);
     return st;
+}
+
+/* CG preconditioned by one V-cycle per iteration (correction scaling off, so
+ * that the preconditioner is a fixed symmetric operator for symmetric A and
+ * n_pre = n_post): the solver / preconditioner pairing of the paper's AmgX
+ * configuration (Appendix A listing: PCG with an AMG V-cycle preconditioner)
+ * applied to this GAMG hierarchy. */
+typedef struct {
+    const orc_gamg *h;
+    vparams vp;
+} vpc_ctx;
+
+static void vcycle_precond(void *ctx, const double *r, double *z) {
+    vpc_ctx *c = (vpc_ctx *)ctx;
+    vcycle(c->h, 0, r, z, &c->vp);
+}
+
+int orc_pcg_gamg(const orc_gamg *h, const double *b, double *x, double tol,
+                 int max_iter, int n_pre, int n_post, double omega,
+                 int transpose, int *iters, double *hist, double *true_res) {
+    omat m = level_mat(&h->lev[0], transpose);
+    vpc_ctx c = {h, {n_pre, n_post, 0, transpose, omega}};
+    return cg_solve(&m, 2, vcycle_precond, &c, b, x, tol, max_iter, iters,
+                    hist, true_res);
 }
 
 /* ---- FP32 V-cycle with an FP64 coarsest level (mixed form) -------------- */

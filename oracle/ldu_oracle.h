@@ -70,6 +70,9 @@ orc_gamg *orc_gamg_build(int32_t n, int64_t nf, const int32_t *own,
                          const double *upper, const double *lower,
                          int n_coarsest, int max_levels, int match_rounds);
 void orc_gamg_free(orc_gamg *h);
+/* new level-0 coefficients; aggregation kept, coarse matrices recomputed */
+void orc_gamg_set_values(orc_gamg *h, const double *diag, const double *upper,
+                         const double *lower);
 int orc_gamg_nlevels(const orc_gamg *h);
 void orc_gamg_level_size(const orc_gamg *h, int level, int64_t *n, int64_t *nf);
 /* agg may be NULL; it is only defined for levels below the coarsest */
@@ -87,6 +90,10 @@ int orc_gamg_solve(const orc_gamg *h, const double *b, double *x, double tol,
                    int max_cycles, int n_pre, int n_post, double omega,
                    int scale, int transpose, int *cycles, double *hist,
                    double *true_res);
+/* CG preconditioned by one V-cycle per iteration (scaling off) */
+int orc_pcg_gamg(const orc_gamg *h, const double *b, double *x, double tol,
+                 int max_iter, int n_pre, int n_post, double omega,
+                 int transpose, int *iters, double *hist, double *true_res);
 /* FP32 V-cycle (coarsest level in FP64) inside FP64 refinement */
 int orc_gamg_mixed(const orc_gamg *h, const double *b, double *x, double tol,
                    int max_refine, int n_pre, int n_post, double omega,

@@ -75,6 +75,7 @@ def lib():
     L.orc_gamg_build.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p,
                                  C.c_int, C.c_int, C.c_int]
     L.orc_gamg_free.argtypes = [vp]
+    L.orc_gamg_set_values.argtypes = [vp, _f64p, _f64p, _f64p]
     L.orc_gamg_nlevels.argtypes = [vp]
     L.orc_gamg_level_size.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(i64)]
     L.orc_gamg_level_export.argtypes = [vp, C.c_int, _i32o, _i32o, _i32o, _f64o,
@@ -84,6 +85,8 @@ def lib():
                                   C.c_int]
     L.orc_gamg_solve.argtypes = [vp, _f64p, _f64p, d, C.c_int, C.c_int, C.c_int, d,
                                  C.c_int, C.c_int, ip, _f64o, dp]
+    L.orc_pcg_gamg.argtypes = [vp, _f64p, _f64p, d, C.c_int, C.c_int, C.c_int, d,
+                               C.c_int, ip, _f64o, dp]
     L.orc_gamg_mixed.argtypes = [vp, _f64p, _f64p, d, C.c_int, C.c_int, C.c_int, d,
                                  C.c_int, C.c_int, ip, _f64o, dp]
     L.orc_coeff_grad.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p,
@@ -210,6 +213,11 @@ class Gamg:
         if h and _lib is not None:
             _lib.orc_gamg_free(h)
 
+    def set_values(self, diag, upper, lower):
+        """New fine-level coefficients; aggregation kept, Galerkin redone."""
+        lib().orc_gamg_set_values(self._h, _c(diag, np.float64),
+                                  _c(upper, np.float64), _c(lower, np.float64))
+
     @property
     def n_levels(self):
         return lib().orc_gamg_nlevels(self._h)
@@ -253,6 +261,19 @@ class Gamg:
                                   float(omega), int(bool(scale)),
                                   int(bool(transpose)), C.byref(k), hist,
                                   C.byref(tr))
+        return SolveResult(st, x, k.value, hist[: k.value + 1].copy(), tr.value)
+
+    def pcg(self, b, x0=None, tol=1e-8, max_iter=10000, n_pre=2, n_post=2,
+            omega=0.75, transpose=False):
+        """CG preconditioned by one V-cycle (correction scaling off)."""
+        x = np.zeros(self.A.n) if x0 is None else _c(x0, np.float64).copy()
+        hist = np.zeros(max_iter + 2)
+        k = C.c_int(0)
+        tr = C.c_double(0.0)
+        st = lib().orc_pcg_gamg(self._h, _c(b, np.float64), x, float(tol),
+                                int(max_iter), int(n_pre), int(n_post),
+                                float(omega), int(bool(transpose)), C.byref(k),
+                                hist, C.byref(tr))
         return SolveResult(st, x, k.value, hist[: k.value + 1].copy(), tr.value)
 
     def solve_mixed(self, b, x0=None, tol=1e-8, max_refine=200, n_pre=2,

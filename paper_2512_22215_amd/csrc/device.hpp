@@ -1,0 +1,154 @@
+// Device-side building blocks shared by the kernels of the library.
+//
+// - for_each_slice: XCD-aware work distribution.  MI355X dispatches
+//   consecutive workgroups round-robin over its 8 XCDs, each with its own L2.
+//   Large grids are therefore split into 8 contiguous row ranges, one per
+//   XCD, and the workgroups of an XCD sweep their range front to back; the
+//   +-nx*ny neighbour band of a cell is then read from the L2 that fetched it
+//   instead of the L2 of another XCD.
+// - deterministic reductions: a fixed butterfly inside the wavefront, a fixed
+//   order across the 4 wavefronts of a block, one partial per block, and the
+//   last block to arrive (integer ticket) sums the partials in a fixed order.
+//   Results are bitwise reproducible run to run; no floating-point atomics.
+// - sell_row: one row of a sliced-ELLPACK product, diagonal first and then
+//   the entries in column order, each product rounded before its addition
+//   (the library is compiled without FMA contraction), which is exactly the
+//   rounding sequence of the lduMatrix face loop for that row.
+#pragma once
+
+#include "internal.hpp"
+
+namespace ldu {
+
+template <class F>
+__device__ __forceinline__ void for_each_slice(int64_t S, F &&f) {
+    const int G = gridDim.x;
+    const int nx = (G >= 64 && (G & 7) == 0) ? 8 : 1;
+    const int64_t x = blockIdx.x % nx;
+    const int64_t j = blockIdx.x / nx;
+    const int64_t Gx = G / nx;
+    const int64_t R = (S + nx - 1) / nx;
+    const int64_t lo = x * R;
+    const int64_t hi = (lo + R < S) ? lo + R : S;
+    const int w = threadIdx.x >> 6;
+    for (int64_t g = j; lo + g * kWavesPerBlock < hi; g += Gx) {
+        const int64_t s = lo + g * kWavesPerBlock + w;
+        if (s < hi) f(s);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// block-wide reduction of K values (slots >= K - M take the max, the others
+// the sum); the result is valid in thread 0
+template <int K, int M = 0>
+__device__ __forceinline__ void block_reduce(double (&v)[K]) {
+    __shared__ double sm[K][kWavesPerBlock];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = (k >= K - M) ? wave_max(v[k]) : wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sm[k][w] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            v[k] = (k >= K - M) ? fmax(fmax(sm[k][0], sm[k][1]), fmax(sm[k][2], sm[k][3]))
+                                : ((sm[k][0] + sm[k][1]) + sm[k][2]) + sm[k][3];
+    }
+}
+
+// grid-wide reduction of K per-thread values (the last M by max); the last
+// block to arrive calls epi(total) in its thread 0.  partials holds
+// K * kMaxGrid doubles.  Every block of the grid must call this exactly once.
+template <int K, int M = 0, class Epi>
+__device__ __forceinline__ void grid_reduce(double (&v)[K], double *partials,
+                                            DevScalars *ds, Epi &&epi) {
+    __shared__ int am_last;
+    block_reduce<K, M>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            __hip_atomic_store(&partials[k * kMaxGrid + blockIdx.x], v[k],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        unsigned t = atomicAdd(&ds->ticket, 1u);
+        am_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!am_last) return;
+    __threadfence();
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double p = __hip_atomic_load(&partials[k * kMaxGrid + b], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+            s[k] = (k >= K - M) ? fmax(s[k], p) : s[k] + p;
+        }
+    }
+    block_reduce<K, M>(s);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&ds->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        epi(s);
+    }
+}
+
+// x accessors for the product kernels
+template <typename T>
+struct Direct {
+    const T *x;
+    __device__ __forceinline__ T operator()(int32_t j) const { return x[j]; }
+};
+template <typename T>
+struct ViaAgg {  // prolonged vector c_j = ec[agg[j]]
+    const T *ec;
+    const int32_t *agg;
+    __device__ __forceinline__ T operator()(int32_t j) const { return ec[agg[j]]; }
+};
+
+// (A x)_i for row i = 64 s + lane of slice s
+template <typename T, class XA>
+__device__ __forceinline__ T sell_row(const SellView<T> &A, int64_t s, int lane,
+                                      int32_t i, const XA &xa) {
+    const int64_t b0 = A.sptr[s];
+    const int w = (int)((A.sptr[s + 1] - b0) >> 6);
+    const int32_t *cp = A.col + b0 + lane;
+    const T *vp = A.val + b0 + lane;
+    T acc = A.diag[i] * xa(i);
+    for (int k = 0; k < w; k += 8) {
+        int32_t c[8];
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (k + u < w) {
+                c[u] = __builtin_nontemporal_load(cp + (int64_t)(k + u) * kWave);
+                v[u] = __builtin_nontemporal_load(vp + (int64_t)(k + u) * kWave);
+            }
+        }
+        T xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k + u < w) xv[u] = xa(c[u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k + u < w) acc = acc + v[u] * xv[u];
+    }
+    return acc;
+}
+
+}  // namespace ldu

@@ -1,0 +1,985 @@
+// GAMG: pairwise agglomeration, Galerkin coarse matrices and the V-cycle.
+//
+// The paper runs OpenFOAM's GAMG for the pressure equation with the
+// Richardson (damped Jacobi) smoother on every level and a diagonal-PCG
+// coarsest solve, its fastest combination (Sec. 4.3, smoother table;
+// Appendix A), and profiles agglomerateMatrix, restrictField, prolongField,
+// scale and Vcycle (Sec. 4.3, kernel time breakdown).  It keeps OpenFOAM's
+// serial CPU coarsening.  Here the coarsening is a parallel handshake
+// matching with a strict total order on faces:
+//   weight w_f = ((|upper_f| + |lower_f|) / 2)^2 / |diag_i diag_j| (the
+//   squared coupling relative to the diagonals, which stays level under
+//   geometric mesh grading), ties broken by a SplitMix64 hash of the face's
+//   (min, max) cell pair, then by the smaller cell index;
+//   each round, every unmatched cell picks its best unmatched neighbour and
+//   mutual picks pair up; rounds stop when one adds no pair or after
+//   match_rounds; an unmatched cell then joins the aggregate of its best
+//   matched neighbour (no cascading) or stays a singleton; aggregates are
+//   numbered by their seed cell (pair minimum or singleton).
+// The result depends only on the matrix, not on the order in which threads
+// run, and equals the greedy matching in that face order.
+//
+// Galerkin coarse matrices A_c = P^T A P (piecewise-constant P) are formed in
+// LDU form with coarse faces sorted by (a, b); each coarse value is summed
+// over its fine faces in ascending face order, and each coarse diagonal over
+// member cells in ascending order and then over the aggregate's internal
+// faces in ascending order.  Summation order is fixed, so the hierarchy is
+// bitwise reproducible.
+#include "device.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace ldu {
+
+__device__ __forceinline__ uint64_t splitmix64_out(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t tie_key(int32_t i, int32_t j) {
+    const uint64_t lo = (uint32_t)(i < j ? i : j), hi = (uint32_t)(i < j ? j : i);
+    return splitmix64_out((lo << 32) | hi);
+}
+// squared diagonally scaled coupling strength (no square root: it rounds the
+// same way on every device)
+__device__ __forceinline__ double strength2(double a, double at, double di, double dj) {
+    const double s = 0.5 * (fabs(a) + fabs(at));
+    const double den = fabs(di) * fabs(dj);
+    return den > 0.0 ? (s * s) / den : s * s;
+}
+__device__ __forceinline__ bool better(double w1, uint64_t h1, int32_t j1, double w2,
+                                       uint64_t h2, int32_t j2) {
+    if (w1 != w2) return w1 > w2;
+    if (h1 != h2) return h1 > h2;
+    return j1 < j2;
+}
+
+static unsigned grid_n(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    g = g > 8192 ? 8192 : (g < 1 ? 1 : g);
+    return (unsigned)g;
+}
+#define GRID_STRIDE(i, n)                                                         \
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); \
+         i += (int64_t)gridDim.x * blockDim.x)
+
+// best neighbour of row i among those whose matched state equals want_matched
+__device__ int32_t best_neighbour(const Sell &A, int32_t i, const int32_t *partner,
+                                  bool want_matched) {
+    const int64_t s = i >> 6, lane = i & 63;
+    const int64_t b0 = A.sptr[s];
+    const int w = (int)((A.sptr[s + 1] - b0) >> 6);
+    int32_t best = -1;
+    double bw = 0.0;
+    uint64_t bh = 0;
+    for (int k = 0; k < w; ++k) {
+        const int64_t pos = b0 + (int64_t)k * kWave + lane;
+        const int32_t c = A.col[pos];
+        if (c == i) continue;  // padding
+        if ((partner[c] >= 0) != want_matched) continue;
+        const double wt = strength2(A.val[pos], A.valT[pos], A.diag[i], A.diag[c]);
+        const uint64_t hk = tie_key(i, c);
+        if (best < 0 || better(wt, hk, c, bw, bh, best)) {
+            best = c;
+            bw = wt;
+            bh = hk;
+        }
+    }
+    return best;
+}
+
+// flags[0] = pair added this round, flags[1] = matching finished
+__global__ void k_match_init(int32_t n, int32_t *partner, int *flags) {
+    GRID_STRIDE(i, n) partner[i] = -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) { flags[0] = 0; flags[1] = 0; }
+}
+__global__ void k_match_pick(Sell A, const int32_t *partner, int32_t *pick, const int *flags) {
+    if (flags[1]) return;
+    GRID_STRIDE(i, A.n) {
+        pick[i] = partner[i] < 0 ? best_neighbour(A, (int32_t)i, partner, false) : -1;
+    }
+}
+__global__ void k_match_pair(int32_t n, const int32_t *pick, int32_t *partner, int *flags) {
+    if (flags[1]) return;
+    GRID_STRIDE(i, n) {
+        const int32_t j = pick[i];
+        if (j >= 0 && pick[j] == (int32_t)i) {
+            partner[i] = j;
+            flags[0] = 1;
+        }
+    }
+}
+__global__ void k_match_round_end(int *flags) {
+    if (!flags[1] && !flags[0]) flags[1] = 1;
+    flags[0] = 0;
+}
+__global__ void k_match_leftover(Sell A, const int32_t *partner, int32_t *join, int32_t *seed) {
+    GRID_STRIDE(i, A.n) {
+        const int32_t p = partner[i];
+        const int32_t jn = p < 0 ? best_neighbour(A, (int32_t)i, partner, true) : -1;
+        join[i] = jn;
+        seed[i] = ((p >= 0 && (int32_t)i < p) || (p < 0 && jn < 0)) ? 1 : 0;
+    }
+}
+__global__ void k_match_assign(int32_t n, const int32_t *partner, const int32_t *join,
+                               const int32_t *rank, int32_t *agg) {
+    GRID_STRIDE(i, n) {
+        const int32_t p = partner[i];
+        int32_t a;
+        if (p >= 0) {
+            a = rank[(int32_t)i < p ? (int32_t)i : p];
+        } else if (join[i] < 0) {
+            a = rank[i];
+        } else {
+            const int32_t j = join[i], pj = partner[j];
+            a = rank[j < pj ? j : pj];
+        }
+        agg[i] = a;
+    }
+}
+
+// aggregate member lists, ascending cell order
+__global__ void k_agg_count(int32_t n, const int32_t *agg, int32_t *cnt) {
+    GRID_STRIDE(i, n) atomicAdd(&cnt[agg[i]], 1);
+}
+__global__ void k_agg_fill(int32_t n, const int32_t *agg, const int32_t *start, int32_t *cursor,
+                           int32_t *cells) {
+    GRID_STRIDE(i, n) {
+        const int32_t a = agg[i];
+        cells[start[a] + atomicAdd(&cursor[a], 1)] = (int32_t)i;
+    }
+}
+__global__ void k_agg_sort(int32_t nc, const int32_t *start, int32_t *cells) {
+    GRID_STRIDE(a, nc) {
+        const int32_t lo = start[a], hi = start[a + 1];
+        for (int32_t k = lo + 1; k < hi; ++k) {
+            const int32_t v = cells[k];
+            int32_t m = k - 1;
+            while (m >= lo && cells[m] > v) { cells[m + 1] = cells[m]; --m; }
+            cells[m + 1] = v;
+        }
+    }
+}
+
+// coarse row a: the sorted distinct aggregates b > a adjacent to a
+__device__ int coarse_row(const Sell &A, const int32_t *agg, const int32_t *start,
+                          const int32_t *cells, int32_t a, int32_t *list, int *overflow) {
+    int m = 0;
+    for (int32_t k = start[a]; k < start[a + 1]; ++k) {
+        const int32_t i = cells[k];
+        const int64_t s = i >> 6, lane = i & 63;
+        const int64_t b0 = A.sptr[s];
+        const int w = (int)((A.sptr[s + 1] - b0) >> 6);
+        for (int e = 0; e < w; ++e) {
+            const int32_t c = A.col[b0 + (int64_t)e * kWave + lane];
+            if (c == i) continue;
+            const int32_t b = agg[c];
+            if (b <= a) continue;
+            int pos = m;  // insertion into the sorted unique list
+            while (pos > 0 && list[pos - 1] > b) --pos;
+            if (pos > 0 && list[pos - 1] == b) continue;
+            if (m >= kMaxCoarseRow) { *overflow = 1; return m; }
+            for (int q = m; q > pos; --q) list[q] = list[q - 1];
+            list[pos] = b;
+            ++m;
+        }
+    }
+    return m;
+}
+__global__ void k_coarse_count(Sell A, int32_t nc, const int32_t *agg, const int32_t *start,
+                               const int32_t *cells, int32_t *cnt, int *overflow) {
+    int32_t list[kMaxCoarseRow];
+    GRID_STRIDE(a, nc) cnt[a] = coarse_row(A, agg, start, cells, (int32_t)a, list, overflow);
+}
+__global__ void k_coarse_fill(Sell A, int32_t nc, const int32_t *agg, const int32_t *start,
+                              const int32_t *cells, const int32_t *cptr, int32_t *cown,
+                              int32_t *cnb, int *overflow) {
+    int32_t list[kMaxCoarseRow];
+    GRID_STRIDE(a, nc) {
+        const int m = coarse_row(A, agg, start, cells, (int32_t)a, list, overflow);
+        for (int k = 0; k < m; ++k) {
+            cown[cptr[a] + k] = (int32_t)a;
+            cnb[cptr[a] + k] = list[k];
+        }
+    }
+}
+
+// coarse face values: fine faces between aggregates a < b in ascending order
+__global__ void k_coarse_values(int64_t ncf, const int32_t *cown, const int32_t *cnb,
+                                const int32_t *agg, const int32_t *start, const int32_t *cells,
+                                const int64_t *ownStart, const int32_t *fnb,
+                                const double *fup, const double *flo, double *cup,
+                                double *clo) {
+    GRID_STRIDE(c, ncf) {
+        const int32_t a = cown[c], b = cnb[c];
+        int32_t ka = start[a], kb = start[b];
+        const int32_t ea = start[a + 1], eb = start[b + 1];
+        double up = 0.0, lo = 0.0;
+        while (ka < ea || kb < eb) {  // merge the two member lists
+            int32_t i;
+            bool in_a;
+            if (kb >= eb || (ka < ea && cells[ka] < cells[kb])) { i = cells[ka++]; in_a = true; }
+            else { i = cells[kb++]; in_a = false; }
+            const int32_t other = in_a ? b : a;
+            for (int64_t f = ownStart[i]; f < ownStart[i + 1]; ++f) {
+                if (agg[fnb[f]] != other) continue;
+                if (in_a) { up += fup[f]; lo += flo[f]; }
+                else { up += flo[f]; lo += fup[f]; }
+            }
+        }
+        cup[c] = up;
+        clo[c] = lo;
+    }
+}
+
+__global__ void k_coarse_diag(int32_t nc, const int32_t *agg, const int32_t *start,
+                              const int32_t *cells, const int64_t *ownStart, const int32_t *fnb,
+                              const double *fdiag, const double *fup, const double *flo,
+                              double *cdiag) {
+    GRID_STRIDE(a, nc) {
+        double d = 0.0;
+        for (int32_t k = start[a]; k < start[a + 1]; ++k) d += fdiag[cells[k]];
+        for (int32_t k = start[a]; k < start[a + 1]; ++k) {
+            const int32_t i = cells[k];
+            for (int64_t f = ownStart[i]; f < ownStart[i + 1]; ++f)
+                if (agg[fnb[f]] == (int32_t)a) d += (fup[f] + flo[f]);
+        }
+        cdiag[a] = d;
+    }
+}
+
+// singular level: |(A 1)_i| <= 1e-12 |diag_i| for every row
+__global__ void k_singular(Sell A, int *flag) {
+    GRID_STRIDE(i, A.n) {
+        const int64_t s = i >> 6, lane = i & 63;
+        const SellView<double> v = A.view(false);
+        struct One { __device__ double operator()(int32_t) const { return 1.0; } };
+        const double y = sell_row(v, s, (int)lane, (int32_t)i, One{});
+        if (!(fabs(y) <= 1e-12 * fabs(A.diag[i]))) atomicAnd(flag, 0);
+    }
+}
+
+// ---------------------------------------------------------------- setup
+// FP32 copies of every level's values; level 0's live with the handle
+static void ensure_f32_levels(ldu_t *h, hipStream_t st) {
+    ensure_f32(h->L0, h->arena, st);
+    h->levels[0].A = h->L0.A;
+    for (size_t l = 1; l < h->levels.size(); ++l) ensure_f32(h->levels[l], h->gamg_arena, st);
+}
+
+static void alloc_work(Level &L, Arena &ar) {
+    L.r = ar.get<double>(L.n);
+    L.e = ar.get<double>(L.n);
+    L.e2 = ar.get<double>(L.n);
+    L.t = ar.get<double>(L.n);
+}
+
+static void coarse_values(ldu_t *h, Level &F, Level &C, hipStream_t st) {
+    if (C.nf > 0)
+        k_coarse_values<<<grid_n(C.nf), kBlock, 0, st>>>(C.nf, C.own, C.nb, F.agg, F.aggStart,
+                                                          F.aggCells, F.ownStart, F.nb, F.upper,
+                                                          F.lower, C.upper, C.lower);
+    k_coarse_diag<<<grid_n(C.n), kBlock, 0, st>>>(C.n, F.agg, F.aggStart, F.aggCells, F.ownStart,
+                                                  F.nb, F.diag, F.upper, F.lower, C.diag);
+    HIP_CHECK(hipGetLastError());
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+static void detect_singular(ldu_t *h, Level &L, hipStream_t st) {
+    k_set_int<<<1, 1, 0, st>>>(h->flag, 1);
+    k_singular<<<grid_n(L.n), kBlock, 0, st>>>(L.A, h->flag);
+    HIP_CHECK(hipMemcpyAsync(h->hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    L.singular = (*h->hflag != 0) && L.n > 0;
+}
+
+// agglomerate level F; returns the number of aggregates
+static int32_t agglomerate(ldu_t *h, Level &F, int match_rounds, Arena &ar, hipStream_t st) {
+    const int32_t n = F.n;
+    Arena tmp;
+    int32_t *partner = tmp.get<int32_t>(n);
+    int32_t *pick = tmp.get<int32_t>(n);
+    int32_t *join = tmp.get<int32_t>(n);
+    int32_t *seed = tmp.get<int32_t>(n);
+    int32_t *rank = tmp.get<int32_t>((size_t)n + 1);
+    int *flags = tmp.get<int>(2);
+    const unsigned g = grid_n(n);
+    k_match_init<<<g, kBlock, 0, st>>>(n, partner, flags);
+    for (int round = 0; round < match_rounds; ++round) {
+        k_match_pick<<<g, kBlock, 0, st>>>(F.A, partner, pick, flags);
+        k_match_pair<<<g, kBlock, 0, st>>>(n, pick, partner, flags);
+        k_match_round_end<<<1, 1, 0, st>>>(flags);
+    }
+    k_match_leftover<<<g, kBlock, 0, st>>>(F.A, partner, join, seed);
+    scan_counts_i32(seed, rank, n, tmp, st);
+    int32_t nc = 0;
+    HIP_CHECK(hipMemcpyAsync(&nc, rank + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    F.nc = nc;
+    F.agg = ar.get<int32_t>(n);
+    k_match_assign<<<g, kBlock, 0, st>>>(n, partner, join, rank, F.agg);
+    int32_t *cnt = tmp.get<int32_t>(nc);
+    int32_t *cursor = tmp.get<int32_t>(nc);
+    HIP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nc, st));
+    HIP_CHECK(hipMemsetAsync(cursor, 0, sizeof(int32_t) * nc, st));
+    k_agg_count<<<g, kBlock, 0, st>>>(n, F.agg, cnt);
+    F.aggStart = ar.get<int32_t>((size_t)nc + 1);
+    scan_counts_i32(cnt, F.aggStart, nc, tmp, st);
+    F.aggCells = ar.get<int32_t>(n);
+    k_agg_fill<<<g, kBlock, 0, st>>>(n, F.agg, F.aggStart, cursor, F.aggCells);
+    k_agg_sort<<<grid_n(nc), kBlock, 0, st>>>(nc, F.aggStart, F.aggCells);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+    return nc;
+}
+
+static void galerkin(ldu_t *h, Level &F, Level &C, Arena &ar, hipStream_t st) {
+    Arena tmp;
+    const int32_t nc = F.nc;
+    int32_t *cnt = tmp.get<int32_t>(nc);
+    int32_t *cptr = tmp.get<int32_t>((size_t)nc + 1);
+    int *overflow = tmp.get<int>(1);
+    HIP_CHECK(hipMemsetAsync(overflow, 0, sizeof(int), st));
+    k_coarse_count<<<grid_n(nc), kBlock, 0, st>>>(F.A, nc, F.agg, F.aggStart, F.aggCells, cnt,
+                                                  overflow);
+    scan_counts_i32(cnt, cptr, nc, tmp, st);
+    int32_t ncf = 0;
+    int ovf = 0;
+    HIP_CHECK(hipMemcpyAsync(&ncf, cptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (ovf) throw Error(LDU_ERR_LIMIT, "coarse level row exceeds the supported width");
+    C.n = nc;
+    C.nf = ncf;
+    C.own = ar.get<int32_t>(ncf);
+    C.nb = ar.get<int32_t>(ncf);
+    C.upper = ar.get<double>(ncf);
+    C.lower = ar.get<double>(ncf);
+    C.diag = ar.get<double>(nc);
+    k_coarse_fill<<<grid_n(nc), kBlock, 0, st>>>(F.A, nc, F.agg, F.aggStart, F.aggCells, cptr,
+                                                 C.own, C.nb, overflow);
+    HIP_CHECK(hipGetLastError());
+    coarse_values(h, F, C, st);
+    HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
+    h->gamg_ready = false;
+    h->levels.clear();
+    h->gamg_arena.release_all();
+    Arena &ar = h->gamg_arena;
+    h->levels.push_back(h->L0);
+    h->levels[0].agg = h->levels[0].aggStart = h->levels[0].aggCells = nullptr;
+    const int maxl = std::min(std::max(o.max_levels, 1), kMaxLevels);
+    while ((int)h->levels.size() < maxl) {
+        const size_t l = h->levels.size() - 1;
+        if (h->levels[l].n <= o.n_coarsest) break;
+        const int32_t nc = agglomerate(h, h->levels[l], o.match_rounds, ar, st);
+        if (100 * (int64_t)nc > 95 * (int64_t)h->levels[l].n) {
+            h->levels[l].agg = nullptr;
+            break;
+        }
+        Level C;
+        galerkin(h, h->levels[l], C, ar, st);
+        build_level_sell(h, ar, C, false, st);
+        h->levels.push_back(C);
+    }
+    for (auto &L : h->levels) alloc_work(L, ar);
+    h->coarse_work = ar.get<double>(4 * (size_t)h->levels.back().n);
+    if (h->L0.A.val32) ensure_f32_levels(h, st);
+    detect_singular(h, h->levels.back(), st);
+    h->gamg_opts = o;
+    h->gamg_ready = true;
+}
+
+// new level-0 values: recompute every coarse matrix on the cached structure
+void gamg_refresh_values(ldu_t *h, hipStream_t st) {
+    if (!h->gamg_ready) return;
+    h->levels[0].A = h->L0.A;
+    for (size_t l = 0; l + 1 < h->levels.size(); ++l) {
+        Level &F = h->levels[l], &C = h->levels[l + 1];
+        coarse_values(h, F, C, st);
+        set_level_values(C, st);
+        refresh_f32(C, st);
+    }
+    detect_singular(h, h->levels.back(), st);
+}
+
+// ---------------------------------------------------------------- V-cycle kernels
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_first(int32_t n, int64_t S, const T *__restrict__ r, const T *__restrict__ D,
+           T *__restrict__ e, T omega, const DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) e[i] = omega * r[i] / D[i];
+    });
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_zero(int32_t n, int64_t S, T *__restrict__ e, const DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) e[i] = T(0);
+    });
+}
+
+// e_out = e + omega (r - A e) / D
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
+            T *__restrict__ eo, T omega, const DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(A.nslices, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < A.n) {
+            const T y = sell_row(A, s, lane, (int32_t)i, Direct<T>{e});
+            eo[i] = e[i] + omega * (r[i] - y) / A.diag[i];
+        }
+    });
+}
+
+// t = r - A e
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_resid(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
+           T *__restrict__ t, const DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(A.nslices, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < A.n) t[i] = r[i] - sell_row(A, s, lane, (int32_t)i, Direct<T>{e});
+    });
+}
+
+// r_c[a] = sum of t over the members of aggregate a, ascending cell order
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_restrict(int32_t nc, const int32_t *__restrict__ start, const int32_t *__restrict__ cells,
+              const T *__restrict__ t, T *__restrict__ rc, const DevScalars *ds) {
+    if (ds->done) return;
+    GRID_STRIDE(a, nc) {
+        T s = T(0);
+        for (int32_t k = start[a]; k < start[a + 1]; ++k) s += t[cells[k]];
+        rc[a] = s;
+    }
+}
+
+// c = P e_c; s = (c . t) / (c . A c), or 1 when c.Ac is ~0
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_scale(SellView<T> A, const T *__restrict__ ec, const int32_t *__restrict__ agg,
+           const T *__restrict__ t, double *partials, DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    double acc[2] = {0.0, 0.0};
+    for_each_slice(A.nslices, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < A.n) {
+            const T ac = sell_row(A, s, lane, (int32_t)i, ViaAgg<T>{ec, agg});
+            const T ci = ec[agg[i]];
+            acc[0] += (double)ci * (double)t[i];
+            acc[1] += (double)ci * (double)ac;
+        }
+    });
+    grid_reduce<2>(acc, partials, ds, [&](const double *v) {
+        ds->s = (isfinite(v[1]) && fabs(v[1]) > 1e-300) ? v[0] / v[1] : 1.0;
+    });
+}
+
+// e += s c
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_correct(int32_t n, int64_t S, const T *__restrict__ ec, const int32_t *__restrict__ agg,
+             T *__restrict__ e, int use_s, const DevScalars *ds) {
+    if (ds->done) return;
+    const T sc = use_s ? (T)ds->s : T(1);
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) e[i] = e[i] + sc * ec[agg[i]];
+    });
+}
+
+// coarsest level: diagonal PCG in FP64 by one workgroup, from e = 0 to
+// ||r|| <= tol ||rhs|| or max_it iterations; a singular level first
+// projects its rhs to zero mean.  w: 3 n doubles of scratch (r, p, q).
+template <int K>
+__device__ __forceinline__ void bcast_sum(double (&v)[K]) {
+    __shared__ double out[K];
+    block_reduce<K>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = out[k];
+    __syncthreads();
+}
+
+template <typename TI>
+__global__ void __launch_bounds__(kBlock)
+k_coarsest(SellView<double> A, const TI *__restrict__ rhs, TI *__restrict__ eo,
+           double *__restrict__ w, int singular, double tol, int max_it, const DevScalars *ds) {
+    if (ds->done) return;
+    const int32_t n = A.n;
+    double *r = w, *p = w + n, *q = w + 2 * (int64_t)n, *x = w + 3 * (int64_t)n;
+    for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+        r[i] = (double)rhs[i];
+        x[i] = 0.0;
+    }
+    __syncthreads();
+    if (singular) {
+        double m[1] = {0.0};
+        for (int32_t i = threadIdx.x; i < n; i += kBlock) m[0] += r[i];
+        bcast_sum<1>(m);
+        const double mean = m[0] / (double)n;
+        for (int32_t i = threadIdx.x; i < n; i += kBlock) r[i] = r[i] - mean;
+        __syncthreads();
+    }
+    double b2[1] = {0.0};
+    for (int32_t i = threadIdx.x; i < n; i += kBlock) b2[0] += r[i] * r[i];
+    bcast_sum<1>(b2);
+    const double bn = sqrt(b2[0]);
+    if (bn > 0.0) {
+        double rz[1] = {0.0};
+        for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+            const double zi = r[i] / A.diag[i];
+            p[i] = zi;
+            rz[0] += r[i] * zi;
+        }
+        bcast_sum<1>(rz);
+        double rho = rz[0];
+        for (int it = 0; it < max_it; ++it) {
+            double pq[1] = {0.0};
+            for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+                const double qi = sell_row(A, i >> 6, i & 63, i, Direct<double>{p});
+                q[i] = qi;
+                pq[0] += p[i] * qi;
+            }
+            bcast_sum<1>(pq);
+            if (!isfinite(pq[0]) || fabs(pq[0]) <= 1e-300) break;
+            const double alpha = rho / pq[0];
+            double acc[2] = {0.0, 0.0};
+            for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+                x[i] = x[i] + alpha * p[i];
+                const double ri = r[i] - alpha * q[i];
+                r[i] = ri;
+                acc[0] += ri * ri;
+                acc[1] += ri * (ri / A.diag[i]);
+            }
+            bcast_sum<2>(acc);
+            if (sqrt(acc[0]) / bn <= tol) break;
+            const double beta = acc[1] / rho;
+            rho = acc[1];
+            for (int32_t i = threadIdx.x; i < n; i += kBlock)
+                p[i] = r[i] / A.diag[i] + beta * p[i];
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += kBlock) eo[i] = (TI)x[i];
+}
+
+// x += e (GAMG correction of the outer FP64 loop)
+__global__ void __launch_bounds__(kBlock)
+k_add(int32_t n, int64_t S, const double *__restrict__ e, double *__restrict__ x,
+      const DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) x[i] = x[i] + e[i];
+    });
+}
+
+// mixed: rhat = fp32(r / ||r||_inf)
+__global__ void __launch_bounds__(kBlock)
+k_cast_scaled(int32_t n, int64_t S, const double *__restrict__ r, float *__restrict__ r32,
+              DevScalars *ds) {
+    if (ds->done) return;
+    const double sc = ds->maxabs;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) r32[i] = (float)(r[i] / sc);
+    });
+    if (blockIdx.x == 0 && threadIdx.x == 0) ds->scale = sc;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_refine_add(int32_t n, int64_t S, const float *__restrict__ d, double *__restrict__ x,
+             const DevScalars *ds) {
+    if (ds->done) return;
+    const double sc = ds->scale;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) x[i] = x[i] + sc * (double)d[i];
+    });
+}
+
+// ---------------------------------------------------------------- V-cycle driver
+struct VCtx {
+    ldu_t *h;
+    const ldu_gamg_opts *o;
+    bool tr;
+    hipStream_t st;
+    double *cw;  // coarsest scratch, 4 n_coarsest doubles
+};
+
+template <typename T>
+static SellView<T> lview(const Level &L, bool tr);
+template <>
+SellView<double> lview<double>(const Level &L, bool tr) { return L.A.view(tr); }
+template <>
+SellView<float> lview<float>(const Level &L, bool tr) { return L.A.view32(tr); }
+
+template <typename T>
+static T *lvec(Level &L, int which);
+template <>
+double *lvec<double>(Level &L, int which) {
+    return which == 0 ? L.r : which == 1 ? L.e : which == 2 ? L.e2 : L.t;
+}
+template <>
+float *lvec<float>(Level &L, int which) {
+    return which == 0 ? L.r32 : which == 1 ? L.e32 : which == 2 ? L.e232 : L.t32;
+}
+
+template <typename T>
+static T *vcycle(const VCtx &c, size_t l, const T *r) {
+    ldu_t *h = c.h;
+    Level &L = h->levels[l];
+    hipStream_t st = c.st;
+    const bool last = (l + 1 == h->levels.size());
+    T *e = lvec<T>(L, 1), *e2 = lvec<T>(L, 2), *t = lvec<T>(L, 3);
+    if (last) {
+        const int maxit = std::max(2 * L.n, 100);
+        k_coarsest<T><<<1, kBlock, 0, st>>>(L.A.view(c.tr), r, e, c.cw, L.singular,
+                                            kCoarsestTol, maxit, h->dev);
+        HIP_CHECK(hipGetLastError());
+        return e;
+    }
+    const SellView<T> A = lview<T>(L, c.tr);
+    const int64_t S = L.A.nslices;
+    const int G = stream_grid_slices(S);
+    const T omega = (T)c.o->omega;
+    if (c.o->n_pre > 0) k_vc_first<T><<<G, kBlock, 0, st>>>(L.n, S, r, A.diag, e, omega, h->dev);
+    else k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
+    for (int k = 1; k < c.o->n_pre; ++k) {
+        k_vc_jacobi<T><<<G, kBlock, 0, st>>>(A, r, e, e2, omega, h->dev);
+        std::swap(e, e2);
+    }
+    k_vc_resid<T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
+    Level &C = h->levels[l + 1];
+    T *rc = lvec<T>(C, 0);
+    k_vc_restrict<T><<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, t, rc, h->dev);
+    const T *ec = vcycle<T>(c, l + 1, rc);
+    if (c.o->scale_correction)
+        k_vc_scale<T><<<G, kBlock, 0, st>>>(A, ec, L.agg, t, h->partials, h->dev);
+    k_vc_correct<T><<<G, kBlock, 0, st>>>(L.n, S, ec, L.agg, e, c.o->scale_correction, h->dev);
+    for (int k = 0; k < c.o->n_post; ++k) {
+        k_vc_jacobi<T><<<G, kBlock, 0, st>>>(A, r, e, e2, omega, h->dev);
+        std::swap(e, e2);
+    }
+    HIP_CHECK(hipGetLastError());
+    return e;
+}
+
+static void ensure_work32(ldu_t *h, hipStream_t st) {
+    ensure_f32_levels(h, st);
+    for (auto &L : h->levels) {
+        if (!L.r32) {
+            L.r32 = h->gamg_arena.get<float>(L.n);
+            L.e32 = h->gamg_arena.get<float>(L.n);
+            L.e232 = h->gamg_arena.get<float>(L.n);
+            L.t32 = h->gamg_arena.get<float>(L.n);
+        }
+    }
+}
+
+static VCtx make_ctx(ldu_t *h, const ldu_gamg_opts &o, bool tr, hipStream_t st) {
+    return VCtx{h, &o, tr, st, h->coarse_work};
+}
+
+static void fill_level_stats(ldu_t *h, ldu_stats *stats) {
+    if (!stats) return;
+    stats->n_levels = (int)h->levels.size();
+    for (int l = 0; l < 64; ++l) {
+        const bool in = l < (int)h->levels.size();
+        stats->level_cells[l] = in ? h->levels[l].n : 0;
+        stats->level_faces[l] = in ? h->levels[l].nf : 0;
+    }
+}
+
+void gamg_vcycle64(ldu_t *h, const double *r, double *e, const ldu_gamg_opts &o, bool tr,
+                   hipStream_t st) {
+    set_scalars_for_solve(h, 0.0, 0, st);
+    VCtx c = make_ctx(h, o, tr, st);
+    double *res = vcycle<double>(c, 0, r);
+    HIP_CHECK(hipMemcpyAsync(e, res, sizeof(double) * h->L0.n, hipMemcpyDeviceToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+}
+
+static int finish_status(const DevScalars &hs) {
+    if (hs.done == kFailed) return hs.status;
+    if (hs.done == kMaxIter) return LDU_NOT_CONVERGED;
+    return LDU_OK;
+}
+
+int gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_gamg_opts &o, bool tr,
+              ldu_stats *stats, hipStream_t st) {
+    Level &L = h->levels[0];
+    const SellView<double> A = L.A.view(tr);
+    const int64_t S = L.A.nslices;
+    const int G = stream_grid_slices(S);
+    ensure_hist(h, o.max_cycles + 2);
+    fill_level_stats(h, stats);
+    if (stats) { stats->refinements = 0; stats->history_count = 0; }
+    set_scalars_for_solve(h, o.rel_tol, o.max_cycles, st);
+    VCtx c = make_ctx(h, o, tr, st);
+    launch_residual_cycle(h, A, b, x, h->r, false, G, st);
+    read_scalars(h, st);
+    DevScalars &hs = *h->host;
+    if (stats) stats->initial_residual = hs.res;
+    if (hs.bnorm == 0.0) {
+        zero_vector(x, L.n, st);
+        if (stats) {
+            stats->iterations = 0;
+            stats->converged = 1;
+            stats->initial_residual = stats->final_residual = 0.0;
+        }
+        copy_history(h, stats, 1, st);
+        return LDU_OK;
+    }
+    while (hs.done == kRunning) {
+        const double *e = vcycle<double>(c, 0, h->r);
+        k_add<<<G, kBlock, 0, st>>>(L.n, S, e, x, h->dev);
+        launch_residual_cycle(h, A, b, x, h->r, false, G, st);
+        read_scalars(h, st);
+    }
+    const int status = finish_status(hs);
+    if (stats) {
+        stats->iterations = hs.iters;
+        stats->final_residual = hs.res;
+        stats->converged = (status == LDU_OK);
+    }
+    copy_history(h, stats, hs.iters + 1, st);
+    return status;
+}
+
+// ---------------------------------------------------------------- CG + V-cycle
+// CG preconditioned by one V-cycle per iteration, correction scaling off so
+// that the preconditioner is one fixed symmetric operator: the pairing of the
+// paper's AmgX configuration (Appendix A listing: PCG with an AMG V-cycle
+// preconditioner) on this GAMG hierarchy.
+
+// p = z; rho = r.z
+__global__ void __launch_bounds__(kBlock)
+k_pg_start(int32_t n, int64_t S, const double *__restrict__ r, const double *__restrict__ z,
+           double *__restrict__ p, double *partials, DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    double acc[1] = {0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            const double zi = z[i];
+            p[i] = zi;
+            acc[0] += r[i] * zi;
+        }
+    });
+    grid_reduce<1>(acc, partials, ds, [&](const double *t) { ds->rho = t[0]; });
+}
+
+// x += alpha p; r -= alpha q; ||r||^2; convergence test
+__global__ void __launch_bounds__(kBlock)
+k_pg_update(int32_t n, int64_t S, double *__restrict__ x, double *__restrict__ r,
+            const double *__restrict__ p, const double *__restrict__ q, double *partials,
+            DevScalars *ds, double *hist) {
+    if (ds->done) return;
+    const double alpha = ds->alpha;
+    const int lane = threadIdx.x & 63;
+    double acc[1] = {0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            x[i] = x[i] + alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            acc[0] += ri * ri;
+        }
+    });
+    grid_reduce<1>(acc, partials, ds, [&](const double *t) {
+        const int it = ds->iters + 1;
+        ds->iters = it;
+        ds->rr = t[0];
+        const double res = sqrt(t[0]) / ds->bnorm;
+        ds->res = res;
+        if (hist) hist[it] = res;
+        if (!isfinite(res)) {
+            ds->status = LDU_ERR_NAN;
+            ds->done = kFailed;
+        } else if (res <= ds->tol) {
+            ds->done = kConverged;
+        } else if (it >= ds->max_iter) {
+            ds->done = kMaxIter;
+        }
+    });
+}
+
+// rho' = r.z; beta = rho'/rho
+__global__ void __launch_bounds__(kBlock)
+k_pg_rz(int32_t n, int64_t S, const double *__restrict__ r, const double *__restrict__ z,
+        double *partials, DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    double acc[1] = {0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) acc[0] += r[i] * z[i];
+    });
+    grid_reduce<1>(acc, partials, ds, [&](const double *t) {
+        ds->beta = t[0] / ds->rho;
+        ds->rho = t[0];
+    });
+}
+
+// p = z + beta p
+__global__ void __launch_bounds__(kBlock)
+k_pg_p(int32_t n, int64_t S, const double *__restrict__ z, double *__restrict__ p,
+       const DevScalars *ds) {
+    if (ds->done) return;
+    const double beta = ds->beta;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) p[i] = z[i] + beta * p[i];
+    });
+}
+
+int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
+                  ldu_stats *stats, hipStream_t st) {
+    ldu_gamg_opts go = h->gamg_opts;
+    go.scale_correction = 0;
+    Level &L = h->levels[0];
+    const SellView<double> A = L.A.view(tr);
+    const int n = L.n;
+    const int64_t S = L.A.nslices;
+    const int G = stream_grid_slices(S);
+    ensure_hist(h, o.max_iter + 2);
+    fill_level_stats(h, stats);
+    if (stats) { stats->refinements = 0; stats->history_count = 0; }
+    set_scalars_for_solve(h, o.rel_tol, o.max_iter, st);
+    VCtx c = make_ctx(h, go, tr, st);
+    launch_residual_plain(h, A, b, x, h->r, true, G, st);
+    read_scalars(h, st);
+    DevScalars &hs = *h->host;
+    if (stats) stats->initial_residual = hs.res;
+    if (hs.bnorm == 0.0) {
+        zero_vector(x, n, st);
+        if (stats) {
+            stats->iterations = 0;
+            stats->converged = 1;
+            stats->initial_residual = stats->final_residual = 0.0;
+        }
+        copy_history(h, stats, 1, st);
+        return LDU_OK;
+    }
+    if (!std::isfinite(hs.res)) throw Error(LDU_ERR_NAN, "non-finite initial residual");
+    double res = hs.res;
+    int status = LDU_OK;
+    const int every = o.check_every > 0 ? o.check_every : 16;
+    while (res > o.rel_tol) {
+        const double *z = vcycle<double>(c, 0, h->r);
+        k_pg_start<<<G, kBlock, 0, st>>>(n, S, h->r, z, h->p, h->partials, h->dev);
+        for (;;) {
+            for (int k = 0; k < every; ++k) {
+                launch_pcg_q(h, A, h->p, h->q, G, st);
+                k_pg_update<<<G, kBlock, 0, st>>>(n, S, x, h->r, h->p, h->q, h->partials,
+                                                  h->dev, h->hist);
+                z = vcycle<double>(c, 0, h->r);
+                k_pg_rz<<<G, kBlock, 0, st>>>(n, S, h->r, z, h->partials, h->dev);
+                k_pg_p<<<G, kBlock, 0, st>>>(n, S, z, h->p, h->dev);
+            }
+            HIP_CHECK(hipGetLastError());
+            read_scalars(h, st);
+            if (hs.done != kRunning) break;
+        }
+        if (hs.done == kFailed) {
+            status = hs.status;
+            break;
+        }
+        launch_residual_plain(h, A, b, x, h->r, false, G, st);
+        read_scalars(h, st);
+        res = hs.res;
+        if (!std::isfinite(res)) { status = LDU_ERR_NAN; break; }
+        if (res <= o.rel_tol) { status = LDU_OK; break; }
+        if (hs.iters >= o.max_iter) { status = LDU_NOT_CONVERGED; break; }
+        set_done(h, kRunning, st);
+    }
+    if (stats) {
+        stats->iterations = hs.iters;
+        stats->final_residual = res;
+        stats->converged = (status == LDU_OK);
+    }
+    copy_history(h, stats, hs.iters + 1, st);
+    return status;
+}
+
+int gamg_mixed(ldu_t *h, const double *b, double *x, const ldu_gamg_opts &o, bool tr,
+               ldu_stats *stats, hipStream_t st) {
+    ensure_work32(h, st);
+    Level &L = h->levels[0];
+    const SellView<double> A = L.A.view(tr);
+    const int64_t S = L.A.nslices;
+    const int G = stream_grid_slices(S);
+    ensure_hist(h, o.max_refine + 2);
+    fill_level_stats(h, stats);
+    if (stats) stats->history_count = 0;
+    set_scalars_for_solve(h, o.rel_tol, o.max_refine, st);
+    VCtx c = make_ctx(h, o, tr, st);
+    launch_residual_cycle(h, A, b, x, h->r, true, G, st);
+    read_scalars(h, st);
+    DevScalars &hs = *h->host;
+    if (stats) stats->initial_residual = hs.res;
+    if (hs.bnorm == 0.0) {
+        zero_vector(x, L.n, st);
+        if (stats) {
+            stats->iterations = 0;
+            stats->refinements = 0;
+            stats->converged = 1;
+            stats->initial_residual = stats->final_residual = 0.0;
+        }
+        copy_history(h, stats, 1, st);
+        return LDU_OK;
+    }
+    while (hs.done == kRunning) {
+        k_cast_scaled<<<G, kBlock, 0, st>>>(L.n, S, h->r, L.r32, h->dev);
+        const float *d = vcycle<float>(c, 0, L.r32);
+        k_refine_add<<<G, kBlock, 0, st>>>(L.n, S, d, x, h->dev);
+        launch_residual_cycle(h, A, b, x, h->r, true, G, st);
+        read_scalars(h, st);
+    }
+    const int status = finish_status(hs);
+    if (stats) {
+        stats->iterations = hs.iters;
+        stats->refinements = hs.iters;
+        stats->final_residual = hs.res;
+        stats->converged = (status == LDU_OK);
+    }
+    copy_history(h, stats, hs.iters + 1, st);
+    return status;
+}
+
+}  // namespace ldu

@@ -1,0 +1,216 @@
+// Internal declarations of the LDU pressure-solve library (gfx950).
+//
+// Data layout in HBM, per multigrid level:
+//  - face form (owner, neighbour, upper, lower: the lduMatrix arrays of
+//    paper Sec. 2.1) plus ownStart[i], the first face owned by cell i;
+//  - a sliced-ELLPACK copy for the product kernels: rows in slices of 64
+//    (one wavefront), slice s holding width_s = max row length in the slice;
+//    entry k of row r = 64 s + lane sits at sptr[s] + 64 k + lane, so a
+//    wavefront streams 64 consecutive int32 columns and 64 consecutive values
+//    per step.  Row entries are column-sorted: the "lower" faces (columns
+//    below the row) first, then the "upper" ones.  Padding entries point at
+//    their own row with value 0.  val holds A, valT holds A^T at the same
+//    positions, so the transposed product runs the same kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "ldu.h"
+
+namespace ldu {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxGrid = 2048;     // streaming kernels: at most this many blocks
+constexpr int kMaxLevels = 64;
+constexpr int kMaxCoarseRow = 128; // widest coarse-level row the setup supports
+constexpr double kCoarsestTol = 1e-10;
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_fail(hipError_t e, const char *what, const char *file, int line);
+#define HIP_CHECK(x)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (x);                                                \
+        if (e_ != hipSuccess) ::ldu::hip_fail(e_, #x, __FILE__, __LINE__); \
+    } while (0)
+
+// ---------------------------------------------------------------- views
+template <typename T>
+struct SellView {
+    int32_t n;
+    int64_t nslices;
+    const int64_t *sptr;
+    const int32_t *col;
+    const T *val;
+    const T *diag;
+};
+
+// scalars shared between the kernels of one solve; device resident
+struct DevScalars {
+    double rr, bb, rz, rho, pq, alpha, beta, res, bnorm, tol;
+    double maxabs, scale;       // mixed: ||r||_inf of the outer residual
+    double r0, inner_tol;       // mixed inner CG
+    double s;                   // GAMG correction scaling factor
+    double mean;                // coarsest: rhs mean
+    int iters, max_iter, done, status;
+    int inner_iters, inner_max, inner_done, pad_;
+    unsigned int ticket;        // grid reduction arrival counter (always 0 between kernels)
+    unsigned int pad2_;
+};
+
+// done codes
+enum { kRunning = 0, kConverged = 1, kMaxIter = 2, kFailed = 3 };
+
+// ---------------------------------------------------------------- storage
+struct DeviceBuffer {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+class Arena {  // owns every device allocation of a handle
+public:
+    ~Arena();
+    void *alloc(size_t bytes);
+    template <typename T>
+    T *get(size_t count) { return static_cast<T *>(alloc(count * sizeof(T))); }
+    void release_all();
+
+private:
+    std::vector<void *> ptrs_;
+};
+
+struct Sell {
+    int32_t n = 0;
+    int64_t nslices = 0, nnz = 0;
+    int maxw = 0;
+    int64_t *sptr = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr, *valT = nullptr;
+    float *val32 = nullptr, *valT32 = nullptr;
+    double *diag = nullptr;
+    float *diag32 = nullptr;
+
+    __host__ __device__ SellView<double> view(bool transpose) const {
+        return {n, nslices, sptr, col, transpose ? valT : val, diag};
+    }
+    __host__ __device__ SellView<float> view32(bool transpose) const {
+        return {n, nslices, sptr, col, transpose ? valT32 : val32, diag32};
+    }
+};
+
+struct Level {
+    int32_t n = 0;
+    int64_t nf = 0;
+    int32_t *own = nullptr, *nb = nullptr;
+    double *upper = nullptr, *lower = nullptr, *diag = nullptr;
+    int64_t *ownStart = nullptr;          // [n+1]
+    int64_t *slotU = nullptr, *slotL = nullptr;  // [nf] positions in the SELL arrays
+    Sell A;
+    // aggregation to the next level (absent on the coarsest level)
+    int32_t nc = 0;
+    int32_t *agg = nullptr, *aggStart = nullptr, *aggCells = nullptr;
+    int singular = 0;                     // coarsest level: A 1 = 0
+    // V-cycle work vectors
+    double *r = nullptr, *e = nullptr, *e2 = nullptr, *t = nullptr;
+    float *r32 = nullptr, *e32 = nullptr, *e232 = nullptr, *t32 = nullptr;
+};
+
+}  // namespace ldu
+
+// the opaque handle of the C ABI
+struct ldu_t {
+    int device = 0;
+    bool poisoned = false;
+    ldu::Arena arena;            // level-0 and solver buffers
+    ldu::Arena gamg_arena;       // hierarchy buffers (rebuilt by gamg_setup)
+    ldu::Level L0;
+    std::vector<ldu::Level> levels;  // levels[0] aliases L0's arrays when built
+    bool gamg_ready = false;
+    ldu_gamg_opts gamg_opts{};
+    bool f32_ready = false;          // FP32 copies of level values exist
+    // solver buffers
+    double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
+    float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+    double *partials = nullptr;      // [4 * kMaxGrid]
+    ldu::DevScalars *dev = nullptr;
+    ldu::DevScalars *host = nullptr; // pinned mirror
+    double *hist = nullptr;          // device residual history
+    int hist_cap = 0;
+    int *flag = nullptr;             // device error flag (validation)
+    int *hflag = nullptr;            // pinned
+    double *coarse_work = nullptr;   // coarsest-level CG scratch (4 n doubles)
+};
+
+namespace ldu {
+
+// ---------------------------------------------------------------- launch helpers
+inline int stream_grid_slices(int64_t nslices) {
+    int64_t g = (nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (g > kMaxGrid) g = kMaxGrid;
+    if (g >= 64) g &= ~int64_t(7);
+    if (g < 1) g = 1;
+    return (int)g;
+}
+inline int64_t slices_of(int64_t n) { return (n + kWave - 1) / kWave; }
+
+// relayout.hip
+void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t st);
+void set_level_values(Level &L, hipStream_t st);   // face values -> SELL values
+void ensure_f32(Level &L, Arena &ar, hipStream_t st);
+void refresh_f32(Level &L, hipStream_t st);
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, Arena &tmp,
+                        hipStream_t st);  // out has n+1 entries
+void scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n, Arena &tmp,
+                     hipStream_t st);     // out has n+1 entries, int32
+void check_finite(ldu_t *h, const double *a, int64_t n, hipStream_t st);
+
+// spmv_pcg.hip
+void launch_amul(const SellView<double> &A, const double *x, double *y, hipStream_t st);
+void launch_amul32(const SellView<float> &A, const float *x, float *y, hipStream_t st);
+void read_scalars(ldu_t *h, hipStream_t st);
+void set_scalars_for_solve(ldu_t *h, double tol, int max_iter, hipStream_t st);
+double residual_norm(ldu_t *h, const Level &L, bool tr, const double *b,
+                     const double *x, double *r_out, hipStream_t st);
+int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o,
+             bool tr, ldu_stats *stats, hipStream_t st);
+int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o,
+              bool tr, ldu_stats *stats, hipStream_t st);
+void ensure_hist(ldu_t *h, int entries);
+void copy_history(ldu_t *h, ldu_stats *stats, int count, hipStream_t st);
+void launch_coeff_grad(const Level &L, const double *lam, const double *x,
+                       double *gd, double *gu, double *gl, hipStream_t st);
+void launch_residual_cycle(ldu_t *h, const SellView<double> &A, const double *b,
+                           const double *x, double *r, bool maxabs, int grid,
+                           hipStream_t st);
+void zero_vector(double *a, int64_t n, hipStream_t st);
+void launch_residual_plain(ldu_t *h, const SellView<double> &A, const double *b,
+                           const double *x, double *r, bool write_hist, int grid,
+                           hipStream_t st);
+void launch_pcg_q(ldu_t *h, const SellView<double> &A, const double *p, double *q, int grid,
+                  hipStream_t st);
+void set_done(ldu_t *h, int done, hipStream_t st);
+
+// gamg.hip
+void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st);
+void gamg_refresh_values(ldu_t *h, hipStream_t st);
+int gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_gamg_opts &o,
+              bool tr, ldu_stats *stats, hipStream_t st);
+int gamg_mixed(ldu_t *h, const double *b, double *x, const ldu_gamg_opts &o,
+               bool tr, ldu_stats *stats, hipStream_t st);
+void gamg_vcycle64(ldu_t *h, const double *r, double *e, const ldu_gamg_opts &o,
+                   bool tr, hipStream_t st);
+int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
+                  ldu_stats *stats, hipStream_t st);
+
+}  // namespace ldu

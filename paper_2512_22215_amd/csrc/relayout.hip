@@ -1,0 +1,357 @@
+// LDU -> sliced-ELLPACK re-layout, value maps and scans (setup kernels).
+//
+// The paper's external-solver path converts OpenFOAM's LDU arrays to a
+// row-ordered (CSR) matrix through a permutation map computed once and reused
+// when the values change (Sec. 3.4).  Here the same idea produces the
+// row-segmented layout the product kernels stream: per row its "lower"
+// entries (faces where the row is the neighbour, i.e. OpenFOAM's losort
+// order) followed by its "upper" entries (faces it owns), column-sorted, and
+// two face -> position maps (slotU, slotL) so that new coefficients are
+// scattered in place without redoing the structure.
+#include "device.hpp"
+
+namespace ldu {
+
+// ---------------------------------------------------------------- scans
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kBlock * kScanItems;
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *total) {
+    __shared__ T sm[kBlock];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        T a = (threadIdx.x >= (unsigned)off) ? sm[threadIdx.x - off] : T(0);
+        __syncthreads();
+        sm[threadIdx.x] += a;
+        __syncthreads();
+    }
+    T incl = sm[threadIdx.x];
+    *total = sm[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scan_partial(const T *in, int64_t n, T *bsum) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += in[base + k];
+    T tot;
+    block_exclusive_scan<T>(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// exclusive scan of nb block sums by one block (in place), total -> bsum[nb]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scan_sums(T *bsum, int64_t nb) {
+    const int64_t per = (nb + kBlock - 1) / kBlock;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    T s = 0;
+    for (int64_t k = lo; k < lo + per && k < nb; ++k) s += bsum[k];
+    T tot;
+    T off = block_exclusive_scan<T>(s, &tot);
+    for (int64_t k = lo; k < lo + per && k < nb; ++k) {
+        T v = bsum[k];
+        bsum[k] = off;
+        off += v;
+    }
+    if (threadIdx.x == 0) bsum[nb] = tot;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scan_final(const T *in, int64_t n, const T *bsum, T *out) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : T(0);
+        s += v[k];
+    }
+    T tot;
+    T off = block_exclusive_scan<T>(s, &tot) + bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = off;
+        off += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = bsum[gridDim.x];
+}
+
+template <typename T>
+static void exclusive_scan(const T *in, T *out, int64_t n, Arena &tmp, hipStream_t st) {
+    const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+    if (nb == 0) {
+        HIP_CHECK(hipMemsetAsync(out, 0, sizeof(T), st));
+        return;
+    }
+    T *bsum = tmp.get<T>(nb + 1);
+    k_scan_partial<T><<<(unsigned)nb, kBlock, 0, st>>>(in, n, bsum);
+    k_scan_sums<T><<<1, kBlock, 0, st>>>(bsum, nb);
+    k_scan_final<T><<<(unsigned)nb, kBlock, 0, st>>>(in, n, bsum, out);
+    HIP_CHECK(hipGetLastError());
+}
+
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, Arena &tmp,
+                        hipStream_t st) {
+    exclusive_scan<int64_t>(in, out, n, tmp, st);
+}
+void scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n, Arena &tmp,
+                     hipStream_t st) {
+    exclusive_scan<int32_t>(cnt, out, n, tmp, st);
+}
+
+// ---------------------------------------------------------------- checks
+__global__ void k_validate(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+                           int *flag) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nf;
+         f += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t o = own[f], b = nb[f];
+        bool bad = o < 0 || o >= b || b >= n;
+        if (f > 0) {
+            const int32_t po = own[f - 1], pb = nb[f - 1];
+            bad = bad || o < po || (o == po && b <= pb);
+        }
+        if (bad) atomicOr(flag, 1);
+    }
+}
+
+__global__ void k_check_finite(const double *a, int64_t n, int *flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(a[i])) atomicOr(flag, 2);
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+void check_finite(ldu_t *h, const double *a, int64_t n, hipStream_t st) {
+    if (n > 0) k_check_finite<<<grid_for(n), kBlock, 0, st>>>(a, n, h->flag);
+}
+
+// ---------------------------------------------------------------- structure
+// ownStart[i] = first face with owner >= i (faces are sorted by owner)
+__global__ void k_own_start(int32_t n, int64_t nf, const int32_t *own, int64_t *ownStart) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = nf;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (own[mid] < i) lo = mid + 1; else hi = mid;
+        }
+        ownStart[i] = lo;
+    }
+}
+
+__global__ void k_count_lower(int64_t nf, const int32_t *nb, int32_t *cntL) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nf;
+         f += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cntL[nb[f]], 1);
+}
+
+// width of slice s (max row length) times 64 = entries in the slice
+__global__ void k_slice_entries(int32_t n, int64_t S, const int64_t *ownStart,
+                                const int32_t *cntL, int64_t *entries) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        int64_t w = 0;
+        for (int l = 0; l < kWave; ++l) {
+            const int64_t i = s * kWave + l;
+            if (i < n) {
+                int64_t d = cntL[i] + (ownStart[i + 1] - ownStart[i]);
+                w = d > w ? d : w;
+            }
+        }
+        entries[s] = w * kWave;
+    }
+}
+
+__device__ __forceinline__ int64_t sell_pos(const int64_t *sptr, int64_t i, int64_t k) {
+    return sptr[i >> 6] + k * kWave + (i & 63);
+}
+
+__global__ void k_fill_upper(int64_t nf, const int32_t *own, const int32_t *nb,
+                             const int64_t *ownStart, const int32_t *cntL,
+                             const int64_t *sptr, int32_t *col, int64_t *slotU) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nf;
+         f += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = own[f];
+        const int64_t pos = sell_pos(sptr, i, cntL[i] + (f - ownStart[i]));
+        col[pos] = nb[f];
+        slotU[f] = pos;
+    }
+}
+
+// lower entries land in arbitrary order within their row; k_sort_lower
+// orders them by column, which makes the final layout deterministic
+__global__ void k_fill_lower(int64_t nf, const int32_t *own, const int32_t *nb,
+                             const int64_t *sptr, int32_t *cursor, int32_t *col,
+                             int64_t *faceAt) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nf;
+         f += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = nb[f];
+        const int k = atomicAdd(&cursor[j], 1);
+        const int64_t pos = sell_pos(sptr, j, k);
+        col[pos] = own[f];
+        faceAt[pos] = f;
+    }
+}
+
+__global__ void k_sort_lower(int32_t n, const int64_t *sptr, const int32_t *cntL,
+                             int32_t *col, int64_t *faceAt, int64_t *slotL) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int m = cntL[j];
+        for (int a = 1; a < m; ++a) {  // insertion sort by column
+            const int64_t pa = sell_pos(sptr, j, a);
+            const int32_t c = col[pa];
+            const int64_t fa = faceAt[pa];
+            int b = a - 1;
+            while (b >= 0 && col[sell_pos(sptr, j, b)] > c) {
+                const int64_t pb = sell_pos(sptr, j, b), pn = sell_pos(sptr, j, b + 1);
+                col[pn] = col[pb];
+                faceAt[pn] = faceAt[pb];
+                --b;
+            }
+            const int64_t pn = sell_pos(sptr, j, b + 1);
+            col[pn] = c;
+            faceAt[pn] = fa;
+        }
+        for (int a = 0; a < m; ++a) {
+            const int64_t pa = sell_pos(sptr, j, a);
+            slotL[faceAt[pa]] = pa;
+        }
+    }
+}
+
+__global__ void k_fill_pad(int32_t n, int64_t S, const int64_t *sptr, const int64_t *ownStart,
+                           const int32_t *cntL, int32_t *col, double *val, double *valT) {
+    const int64_t rows = S * kWave;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = i >> 6;
+        const int64_t w = (sptr[s + 1] - sptr[s]) >> 6;
+        const int64_t d = (i < n) ? cntL[i] + (ownStart[i + 1] - ownStart[i]) : 0;
+        for (int64_t k = d; k < w; ++k) {
+            const int64_t pos = sell_pos(sptr, i, k);
+            col[pos] = (i < n) ? (int32_t)i : 0;
+            val[pos] = 0.0;
+            valT[pos] = 0.0;
+        }
+    }
+}
+
+__global__ void k_set_values(int64_t nf, const int64_t *slotU, const int64_t *slotL,
+                             const double *upper, const double *lower, double *val,
+                             double *valT) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nf;
+         f += (int64_t)gridDim.x * blockDim.x) {
+        const double u = upper[f], l = lower[f];
+        const int64_t pu = slotU[f], pl = slotL[f];
+        val[pu] = u;
+        val[pl] = l;
+        valT[pu] = l;
+        valT[pl] = u;
+    }
+}
+
+__global__ void k_to_f32(const double *a, float *b, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t st) {
+    const int32_t n = L.n;
+    const int64_t nf = L.nf;
+    const int64_t S = slices_of(n);
+    Arena tmp;
+    if (validate) {
+        HIP_CHECK(hipMemsetAsync(h->flag, 0, sizeof(int), st));
+        if (nf > 0)
+            k_validate<<<grid_for(nf), kBlock, 0, st>>>(n, nf, L.own, L.nb, h->flag);
+        check_finite(h, L.diag, n, st);
+        check_finite(h, L.upper, nf, st);
+        check_finite(h, L.lower, nf, st);
+        HIP_CHECK(hipMemcpyAsync(h->hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        if (*h->hflag & 1) throw Error(LDU_ERR_ADDR, "face addressing violates 0 <= owner < neighbour < nCells, sorted by (owner, neighbour), no duplicates");
+        if (*h->hflag & 2) throw Error(LDU_ERR_NAN, "non-finite coefficient");
+    }
+    L.ownStart = ar.get<int64_t>(n + 1);
+    k_own_start<<<grid_for(n + 1), kBlock, 0, st>>>(n, nf, L.own, L.ownStart);
+    int32_t *cntL = tmp.get<int32_t>(n);
+    HIP_CHECK(hipMemsetAsync(cntL, 0, sizeof(int32_t) * n, st));
+    if (nf > 0) k_count_lower<<<grid_for(nf), kBlock, 0, st>>>(nf, L.nb, cntL);
+    int64_t *entries = tmp.get<int64_t>(S);
+    k_slice_entries<<<grid_for(S), kBlock, 0, st>>>(n, S, L.ownStart, cntL, entries);
+    L.A.sptr = ar.get<int64_t>(S + 1);
+    exclusive_scan_i64(entries, L.A.sptr, S, tmp, st);
+    int64_t nnz = 0;
+    HIP_CHECK(hipMemcpyAsync(&nnz, L.A.sptr + S, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    L.A.n = n;
+    L.A.nslices = S;
+    L.A.nnz = nnz;
+    L.A.col = ar.get<int32_t>(nnz);
+    L.A.val = ar.get<double>(nnz);
+    L.A.valT = ar.get<double>(nnz);
+    L.A.diag = L.diag;
+    L.slotU = ar.get<int64_t>(nf);
+    L.slotL = ar.get<int64_t>(nf);
+    if (nf > 0) {
+        k_fill_upper<<<grid_for(nf), kBlock, 0, st>>>(nf, L.own, L.nb, L.ownStart, cntL,
+                                                     L.A.sptr, L.A.col, L.slotU);
+        int32_t *cursor = tmp.get<int32_t>(n);
+        int64_t *faceAt = tmp.get<int64_t>(nnz);
+        HIP_CHECK(hipMemsetAsync(cursor, 0, sizeof(int32_t) * n, st));
+        k_fill_lower<<<grid_for(nf), kBlock, 0, st>>>(nf, L.own, L.nb, L.A.sptr, cursor,
+                                                     L.A.col, faceAt);
+        k_sort_lower<<<grid_for(n), kBlock, 0, st>>>(n, L.A.sptr, cntL, L.A.col, faceAt,
+                                                    L.slotL);
+    }
+    k_fill_pad<<<grid_for(S * kWave), kBlock, 0, st>>>(n, S, L.A.sptr, L.ownStart, cntL,
+                                                      L.A.col, L.A.val, L.A.valT);
+    HIP_CHECK(hipGetLastError());
+    set_level_values(L, st);
+    // widest slice (informational, also bounds coarse-level rows)
+    std::vector<int64_t> hs(S + 1);
+    HIP_CHECK(hipMemcpyAsync(hs.data(), L.A.sptr, sizeof(int64_t) * (S + 1),
+                             hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));  // tmp is released after this point
+    int64_t mw = 0;
+    for (int64_t s = 0; s < S; ++s) mw = std::max(mw, (hs[s + 1] - hs[s]) / kWave);
+    L.A.maxw = (int)mw;
+}
+
+void set_level_values(Level &L, hipStream_t st) {
+    if (L.nf > 0)
+        k_set_values<<<grid_for(L.nf), kBlock, 0, st>>>(L.nf, L.slotU, L.slotL, L.upper,
+                                                        L.lower, L.A.val, L.A.valT);
+    HIP_CHECK(hipGetLastError());
+}
+
+void refresh_f32(Level &L, hipStream_t st) {
+    if (!L.A.val32) return;
+    k_to_f32<<<grid_for(L.A.nnz), kBlock, 0, st>>>(L.A.val, L.A.val32, L.A.nnz);
+    k_to_f32<<<grid_for(L.A.nnz), kBlock, 0, st>>>(L.A.valT, L.A.valT32, L.A.nnz);
+    k_to_f32<<<grid_for(L.n), kBlock, 0, st>>>(L.diag, L.A.diag32, L.n);
+    HIP_CHECK(hipGetLastError());
+}
+
+void ensure_f32(Level &L, Arena &ar, hipStream_t st) {
+    if (L.A.val32) return;
+    L.A.val32 = ar.get<float>(L.A.nnz);
+    L.A.valT32 = ar.get<float>(L.A.nnz);
+    L.A.diag32 = ar.get<float>(L.n);
+    refresh_f32(L, st);
+}
+
+}  // namespace ldu

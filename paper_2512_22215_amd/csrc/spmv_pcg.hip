@@ -1,0 +1,561 @@
+// Amul / Tmul and the conjugate-gradient solvers.
+//
+// Amul is the sparse product of the lduMatrix (the "SpMVM (Amul + Tmul)" row of
+// the kernel time breakdown, Sec. 4.3).  It is HBM-bound (about 0.15 flop per
+// byte), so it is a pure streaming kernel: no matrix cores, coalesced 64-wide
+// streams of columns and values, the x gather served from L2, and an
+// atomic-free row ownership (each row is summed by exactly one lane).
+//
+// PCG with the diagonal preconditioner (Appendix A) runs as three fused
+// kernels per iteration, with every scalar (rho, alpha, beta, residual) kept in
+// device memory and a device "done" flag that freezes the iteration at the
+// first iterate meeting the tolerance; the host only reads the scalars every
+// check_every iterations, instead of synchronising after each kernel as the
+// paper's executor does (Sec. 4.3, CUDA API statistics).
+#include "device.hpp"
+
+#include <cmath>
+
+namespace ldu {
+
+// ---------------------------------------------------------------- products
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_amul(SellView<T> A, const T *__restrict__ x,
+                                                 T *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    for_each_slice(A.nslices, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < A.n) y[i] = sell_row(A, s, lane, (int32_t)i, Direct<T>{x});
+    });
+}
+
+void launch_amul(const SellView<double> &A, const double *x, double *y, hipStream_t st) {
+    k_amul<double><<<stream_grid_slices(A.nslices), kBlock, 0, st>>>(A, x, y);
+    HIP_CHECK(hipGetLastError());
+}
+void launch_amul32(const SellView<float> &A, const float *x, float *y, hipStream_t st) {
+    k_amul<float><<<stream_grid_slices(A.nslices), kBlock, 0, st>>>(A, x, y);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- scalars
+__global__ void k_init_scalars(DevScalars *ds, double tol, int max_iter) {
+    DevScalars z{};
+    z.tol = tol;
+    z.max_iter = max_iter;
+    *ds = z;
+}
+__global__ void k_set_done(DevScalars *ds, int done) { ds->done = done; }
+void set_done(ldu_t *h, int done, hipStream_t st) {
+    k_set_done<<<1, 1, 0, st>>>(h->dev, done);
+    HIP_CHECK(hipGetLastError());
+}
+
+void set_scalars_for_solve(ldu_t *h, double tol, int max_iter, hipStream_t st) {
+    k_init_scalars<<<1, 1, 0, st>>>(h->dev, tol, max_iter);
+    HIP_CHECK(hipGetLastError());
+}
+
+void read_scalars(ldu_t *h, hipStream_t st) {
+    HIP_CHECK(hipMemcpyAsync(h->host, h->dev, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void ensure_hist(ldu_t *h, int entries) {
+    if (entries <= h->hist_cap) return;
+    h->hist = h->arena.get<double>(entries);
+    h->hist_cap = entries;
+}
+
+void copy_history(ldu_t *h, ldu_stats *stats, int count, hipStream_t st) {
+    if (!stats) return;
+    stats->history_count = 0;
+    if (!stats->history || stats->history_len <= 0 || count <= 0) return;
+    int m = count < stats->history_len ? count : stats->history_len;
+    if (m > h->hist_cap) m = h->hist_cap;
+    HIP_CHECK(hipMemcpyAsync(stats->history, h->hist, sizeof(double) * m,
+                             hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    stats->history_count = m;
+}
+
+// ---------------------------------------------------------------- residual
+// r = b - A x, plus ||r||^2, ||b||^2 and, when P is set, p = D^-1 r (or r)
+// and rho = r.p; MAXABS adds ||r||_inf.  Epilogue modes:
+//   kResPlain  : scalars only (true residual, CG (re)start)
+//   kResCycle  : GAMG/refinement outer loop, honours and sets the done flag
+enum { kResPlain = 0, kResCycle = 1 };
+
+template <bool P, bool MAXABS>
+__global__ void __launch_bounds__(kBlock)
+k_residual(SellView<double> A, const double *__restrict__ b, const double *__restrict__ x,
+           double *__restrict__ r, double *__restrict__ p, int precond, int mode,
+           int write_hist, double *partials, DevScalars *ds, double *hist) {
+    if (mode == kResCycle && ds->done) return;
+    const int lane = threadIdx.x & 63;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // rr, bb, rho, maxabs
+    for_each_slice(A.nslices, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < A.n) {
+            const double bi = b[i];
+            const double ri = bi - sell_row(A, s, lane, (int32_t)i, Direct<double>{x});
+            r[i] = ri;
+            acc[0] += ri * ri;
+            acc[1] += bi * bi;
+            if (P) {
+                const double zi = precond ? ri / A.diag[i] : ri;
+                p[i] = zi;
+                acc[2] += ri * zi;
+            }
+            if (MAXABS) acc[3] = fmax(acc[3], fabs(ri));
+        }
+    });
+    grid_reduce<4, 1>(acc, partials, ds, [&](const double *t) {
+        ds->rr = t[0];
+        ds->bb = t[1];
+        ds->bnorm = sqrt(t[1]);
+        ds->maxabs = t[3];
+        if (P) ds->rho = t[2];
+        const double res = ds->bnorm > 0.0 ? sqrt(t[0]) / ds->bnorm : 0.0;
+        ds->res = res;
+        const int it = ds->iters;
+        if (write_hist && hist) hist[it] = res;
+        if (mode == kResCycle) {
+            if (!isfinite(res)) {
+                ds->status = LDU_ERR_NAN;
+                ds->done = kFailed;
+            } else if (res <= ds->tol) {
+                ds->done = kConverged;
+            } else if (it >= ds->max_iter) {
+                ds->done = kMaxIter;
+            } else {
+                ds->iters = it + 1;
+            }
+        }
+    });
+}
+
+void launch_residual_cycle(ldu_t *h, const SellView<double> &A, const double *b,
+                           const double *x, double *r, bool maxabs, int grid,
+                           hipStream_t st) {
+    if (maxabs)
+        k_residual<false, true><<<grid, kBlock, 0, st>>>(A, b, x, r, nullptr, 0, kResCycle, 1,
+                                                         h->partials, h->dev, h->hist);
+    else
+        k_residual<false, false><<<grid, kBlock, 0, st>>>(A, b, x, r, nullptr, 0, kResCycle, 1,
+                                                          h->partials, h->dev, h->hist);
+    HIP_CHECK(hipGetLastError());
+}
+
+void launch_residual_plain(ldu_t *h, const SellView<double> &A, const double *b,
+                           const double *x, double *r, bool write_hist, int grid,
+                           hipStream_t st) {
+    k_residual<false, false><<<grid, kBlock, 0, st>>>(A, b, x, r, nullptr, 0, kResPlain,
+                                                      write_hist ? 1 : 0, h->partials, h->dev,
+                                                      h->hist);
+    HIP_CHECK(hipGetLastError());
+}
+
+double residual_norm(ldu_t *h, const Level &L, bool tr, const double *b, const double *x,
+                     double *r_out, hipStream_t st) {
+    k_residual<false, false><<<stream_grid_slices(L.A.nslices), kBlock, 0, st>>>(
+        L.A.view(tr), b, x, r_out, nullptr, 0, kResPlain, 0, h->partials, h->dev, nullptr);
+    HIP_CHECK(hipGetLastError());
+    read_scalars(h, st);
+    return h->host->res;
+}
+
+// ---------------------------------------------------------------- PCG, FP64
+// q = A p and p.q -> alpha = rho / p.q
+__global__ void __launch_bounds__(kBlock)
+k_pcg_q(SellView<double> A, const double *__restrict__ p, double *__restrict__ q,
+        double *partials, DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    double acc[1] = {0.0};
+    for_each_slice(A.nslices, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < A.n) {
+            const double qi = sell_row(A, s, lane, (int32_t)i, Direct<double>{p});
+            q[i] = qi;
+            acc[0] += p[i] * qi;
+        }
+    });
+    grid_reduce<1>(acc, partials, ds, [&](const double *t) {
+        const double pq = t[0];
+        ds->pq = pq;
+        if (!isfinite(pq) || fabs(pq) <= 1e-300) {
+            ds->status = LDU_ERR_BREAKDOWN;
+            ds->done = kFailed;
+        } else {
+            ds->alpha = ds->rho / pq;
+        }
+    });
+}
+
+void launch_pcg_q(ldu_t *h, const SellView<double> &A, const double *p, double *q, int grid,
+                  hipStream_t st) {
+    k_pcg_q<<<grid, kBlock, 0, st>>>(A, p, q, h->partials, h->dev);
+}
+
+// x += alpha p; r -= alpha q; ||r||^2 and r.D^-1 r; convergence test
+__global__ void __launch_bounds__(kBlock)
+k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restrict__ x,
+             double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ q,
+             int precond, double *partials, DevScalars *ds, double *hist) {
+    if (ds->done) return;
+    const double alpha = ds->alpha;
+    const int lane = threadIdx.x & 63;
+    double acc[2] = {0.0, 0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            const double xi = x[i] + alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            x[i] = xi;
+            r[i] = ri;
+            const double zi = precond ? ri / D[i] : ri;
+            acc[0] += ri * ri;
+            acc[1] += ri * zi;
+        }
+    });
+    grid_reduce<2>(acc, partials, ds, [&](const double *t) {
+        const int it = ds->iters + 1;
+        ds->iters = it;
+        ds->rr = t[0];
+        const double res = sqrt(t[0]) / ds->bnorm;
+        ds->res = res;
+        if (hist) hist[it] = res;
+        if (!isfinite(res)) {
+            ds->status = LDU_ERR_NAN;
+            ds->done = kFailed;
+        } else if (res <= ds->tol) {
+            ds->done = kConverged;
+        } else if (it >= ds->max_iter) {
+            ds->done = kMaxIter;
+        } else {
+            ds->beta = t[1] / ds->rho;
+            ds->rho = t[1];
+        }
+    });
+}
+
+// p = D^-1 r + beta p
+__global__ void __launch_bounds__(kBlock)
+k_pcg_p(int32_t n, int64_t S, const double *__restrict__ D, const double *__restrict__ r,
+        double *__restrict__ p, int precond, const DevScalars *ds) {
+    if (ds->done) return;
+    const double beta = ds->beta;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            const double zi = precond ? r[i] / D[i] : r[i];
+            p[i] = zi + beta * p[i];
+        }
+    });
+}
+
+__global__ void k_fill(double *a, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+static void fill(double *a, int64_t n, double v, hipStream_t st) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    g = g > 4096 ? 4096 : (g < 1 ? 1 : g);
+    k_fill<<<(unsigned)g, kBlock, 0, st>>>(a, n, v);
+}
+void zero_vector(double *a, int64_t n, hipStream_t st) {
+    fill(a, n, 0.0, st);
+    HIP_CHECK(hipStreamSynchronize(st));
+}
+
+static void fill_stats_common(ldu_stats *stats) {
+    if (!stats) return;
+    stats->refinements = 0;
+    stats->n_levels = 0;
+    stats->history_count = 0;
+}
+
+int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
+             ldu_stats *stats, hipStream_t st) {
+    const Level &L = h->L0;
+    const SellView<double> A = L.A.view(tr);
+    const int n = L.n;
+    const int64_t S = L.A.nslices;
+    const int G = stream_grid_slices(S);
+    const int precond = o.precond ? 1 : 0;
+    ensure_hist(h, o.max_iter + 2);
+    fill_stats_common(stats);
+    set_scalars_for_solve(h, o.rel_tol, o.max_iter, st);
+    k_residual<true, false><<<G, kBlock, 0, st>>>(A, b, x, h->r, h->p, precond, kResPlain, 1,
+                                                  h->partials, h->dev, h->hist);
+    HIP_CHECK(hipGetLastError());
+    read_scalars(h, st);
+    DevScalars &hs = *h->host;
+    if (stats) stats->initial_residual = hs.res;
+    if (hs.bnorm == 0.0) {
+        fill(x, n, 0.0, st);
+        HIP_CHECK(hipStreamSynchronize(st));
+        if (stats) {
+            stats->iterations = 0;
+            stats->converged = 1;
+            stats->initial_residual = stats->final_residual = 0.0;
+        }
+        copy_history(h, stats, 1, st);
+        return LDU_OK;
+    }
+    if (!std::isfinite(hs.res)) throw Error(LDU_ERR_NAN, "non-finite initial residual");
+    double res = hs.res;
+    int status = LDU_OK;
+    const int every = o.check_every > 0 ? o.check_every : 16;
+    while (res > o.rel_tol) {
+        for (;;) {
+            for (int k = 0; k < every; ++k) {
+                k_pcg_q<<<G, kBlock, 0, st>>>(A, h->p, h->q, h->partials, h->dev);
+                k_pcg_update<<<G, kBlock, 0, st>>>(n, S, A.diag, x, h->r, h->p, h->q, precond,
+                                                   h->partials, h->dev, h->hist);
+                k_pcg_p<<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->p, precond, h->dev);
+            }
+            HIP_CHECK(hipGetLastError());
+            read_scalars(h, st);
+            if (hs.done != kRunning) break;
+        }
+        if (hs.done == kFailed) {
+            status = hs.status;
+            break;
+        }
+        // true residual; restart from it if the recursive one drifted
+        k_residual<true, false><<<G, kBlock, 0, st>>>(A, b, x, h->r, h->p, precond, kResPlain,
+                                                      0, h->partials, h->dev, nullptr);
+        HIP_CHECK(hipGetLastError());
+        read_scalars(h, st);
+        res = hs.res;
+        if (!std::isfinite(res)) { status = LDU_ERR_NAN; break; }
+        if (res <= o.rel_tol) { status = LDU_OK; break; }
+        if (hs.iters >= o.max_iter) { status = LDU_NOT_CONVERGED; break; }
+        k_set_done<<<1, 1, 0, st>>>(h->dev, kRunning);
+    }
+    const int iters = hs.iters;
+    if (stats) {
+        stats->iterations = iters;
+        stats->final_residual = res;
+        stats->converged = (status == LDU_OK);
+    }
+    copy_history(h, stats, iters + 1, st);
+    return status;
+}
+
+// ---------------------------------------------------------------- PCG, mixed
+// Outer FP64 refinement with inner FP32 CG.  Inner dot products accumulate
+// in FP64; alpha and beta are formed in FP64 and rounded to FP32.
+
+// rhat = fp32(r / s), d = 0, z = rhat / D32, p = z; ||rhat||^2 and rhat.z
+__global__ void __launch_bounds__(kBlock)
+k_mx_start(int32_t n, int64_t S, const double *__restrict__ r, const float *__restrict__ D,
+           float *__restrict__ r32, float *__restrict__ d32, float *__restrict__ p32,
+           double *partials, DevScalars *ds) {
+    if (ds->done) return;
+    const double sc = ds->maxabs;
+    const int lane = threadIdx.x & 63;
+    double acc[2] = {0.0, 0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            const float ri = (float)(r[i] / sc);
+            const float zi = ri / D[i];
+            r32[i] = ri;
+            d32[i] = 0.0f;
+            p32[i] = zi;
+            acc[0] += (double)ri * (double)ri;
+            acc[1] += (double)ri * (double)zi;
+        }
+    });
+    grid_reduce<2>(acc, partials, ds, [&](const double *t) {
+        ds->scale = sc;
+        ds->r0 = sqrt(t[0]);
+        ds->rho = t[1];
+        ds->inner_iters = 0;
+        ds->inner_done = !(ds->r0 > 0.0);
+    });
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_mx_q(SellView<float> A, const float *__restrict__ p, float *__restrict__ q, double *partials,
+       DevScalars *ds) {
+    if (ds->done || ds->inner_done) return;
+    const int lane = threadIdx.x & 63;
+    double acc[1] = {0.0};
+    for_each_slice(A.nslices, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < A.n) {
+            const float qi = sell_row(A, s, lane, (int32_t)i, Direct<float>{p});
+            q[i] = qi;
+            acc[0] += (double)p[i] * (double)qi;
+        }
+    });
+    grid_reduce<1>(acc, partials, ds, [&](const double *t) {
+        const double pq = t[0];
+        if (!isfinite(pq) || fabs(pq) <= 1e-300) {
+            ds->inner_done = 1;
+        } else {
+            ds->alpha = ds->rho / pq;
+        }
+    });
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_mx_update(int32_t n, int64_t S, const float *__restrict__ D, float *__restrict__ d,
+            float *__restrict__ r, const float *__restrict__ p, const float *__restrict__ q,
+            double *partials, DevScalars *ds) {
+    if (ds->done || ds->inner_done) return;
+    const float af = (float)ds->alpha;
+    const int lane = threadIdx.x & 63;
+    double acc[2] = {0.0, 0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            const float di = d[i] + af * p[i];
+            const float ri = r[i] - af * q[i];
+            d[i] = di;
+            r[i] = ri;
+            const float zi = ri / D[i];
+            acc[0] += (double)ri * (double)ri;
+            acc[1] += (double)ri * (double)zi;
+        }
+    });
+    grid_reduce<2>(acc, partials, ds, [&](const double *t) {
+        const int it = ds->inner_iters + 1;
+        ds->inner_iters = it;
+        if (sqrt(t[0]) <= ds->inner_tol * ds->r0 || it >= ds->inner_max) {
+            ds->inner_done = 1;
+        } else {
+            ds->beta = t[1] / ds->rho;
+            ds->rho = t[1];
+        }
+    });
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_mx_p(int32_t n, int64_t S, const float *__restrict__ D, const float *__restrict__ r,
+       float *__restrict__ p, const DevScalars *ds) {
+    if (ds->done || ds->inner_done) return;
+    const float bf = (float)ds->beta;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) p[i] = r[i] / D[i] + bf * p[i];
+    });
+}
+
+// x += s * fp64(d)
+__global__ void __launch_bounds__(kBlock)
+k_mx_refine(int32_t n, int64_t S, const float *__restrict__ d, double *__restrict__ x,
+            const DevScalars *ds) {
+    if (ds->done) return;
+    const double sc = ds->scale;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) x[i] = x[i] + sc * (double)d[i];
+    });
+}
+
+__global__ void k_mx_set_inner(DevScalars *ds, double inner_tol, int inner_max) {
+    ds->inner_tol = inner_tol;
+    ds->inner_max = inner_max;
+}
+
+int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
+              ldu_stats *stats, hipStream_t st) {
+    Level &L = h->L0;
+    ensure_f32(L, h->arena, st);
+    const SellView<double> A = L.A.view(tr);
+    const SellView<float> A32 = L.A.view32(tr);
+    const int n = L.n;
+    const int64_t S = L.A.nslices;
+    const int G = stream_grid_slices(S);
+    ensure_hist(h, o.max_refine + 2);
+    fill_stats_common(stats);
+    set_scalars_for_solve(h, o.rel_tol, o.max_refine, st);
+    k_mx_set_inner<<<1, 1, 0, st>>>(h->dev, o.inner_rel_tol, o.inner_max_iter);
+    k_residual<false, true><<<G, kBlock, 0, st>>>(A, b, x, h->r, nullptr, 0, kResCycle, 1,
+                                                  h->partials, h->dev, h->hist);
+    HIP_CHECK(hipGetLastError());
+    read_scalars(h, st);
+    DevScalars &hs = *h->host;
+    if (stats) stats->initial_residual = hs.res;
+    if (hs.bnorm == 0.0) {
+        fill(x, n, 0.0, st);
+        HIP_CHECK(hipStreamSynchronize(st));
+        if (stats) {
+            stats->iterations = 0;
+            stats->converged = 1;
+            stats->initial_residual = stats->final_residual = 0.0;
+        }
+        copy_history(h, stats, 1, st);
+        return LDU_OK;
+    }
+    const int every = o.check_every > 0 ? o.check_every : 16;
+    long long inner_total = 0;
+    while (hs.done == kRunning) {
+        k_mx_start<<<G, kBlock, 0, st>>>(n, S, h->r, A32.diag, h->r32, h->d32, h->p32,
+                                         h->partials, h->dev);
+        for (;;) {
+            for (int k = 0; k < every; ++k) {
+                k_mx_q<<<G, kBlock, 0, st>>>(A32, h->p32, h->q32, h->partials, h->dev);
+                k_mx_update<<<G, kBlock, 0, st>>>(n, S, A32.diag, h->d32, h->r32, h->p32,
+                                                  h->q32, h->partials, h->dev);
+                k_mx_p<<<G, kBlock, 0, st>>>(n, S, A32.diag, h->r32, h->p32, h->dev);
+            }
+            HIP_CHECK(hipGetLastError());
+            read_scalars(h, st);
+            if (hs.inner_done) break;
+        }
+        inner_total += hs.inner_iters;
+        k_mx_refine<<<G, kBlock, 0, st>>>(n, S, h->d32, x, h->dev);
+        k_residual<false, true><<<G, kBlock, 0, st>>>(A, b, x, h->r, nullptr, 0, kResCycle, 1,
+                                                      h->partials, h->dev, h->hist);
+        HIP_CHECK(hipGetLastError());
+        read_scalars(h, st);
+    }
+    int status = LDU_OK;
+    if (hs.done == kFailed) status = hs.status;
+    else if (hs.done == kMaxIter) status = LDU_NOT_CONVERGED;
+    if (stats) {
+        stats->iterations = (int)inner_total;
+        stats->refinements = hs.iters;
+        stats->final_residual = hs.res;
+        stats->converged = (status == LDU_OK);
+    }
+    copy_history(h, stats, hs.iters + 1, st);
+    return status;
+}
+
+// ---------------------------------------------------------------- adjoint gradients
+__global__ void k_coeff_grad(int32_t n, int64_t nf, const int32_t *__restrict__ own,
+                             const int32_t *__restrict__ nb, const double *__restrict__ lam,
+                             const double *__restrict__ x, double *gd, double *gu, double *gl) {
+    const int64_t m = nf > n ? nf : n;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (gd && k < n) gd[k] = -(lam[k] * x[k]);
+        if (k < nf) {
+            const int32_t o = own[k], b = nb[k];
+            if (gu) gu[k] = -(lam[o] * x[b]);
+            if (gl) gl[k] = -(lam[b] * x[o]);
+        }
+    }
+}
+
+void launch_coeff_grad(const Level &L, const double *lam, const double *x, double *gd,
+                       double *gu, double *gl, hipStream_t st) {
+    const int64_t m = L.nf > L.n ? L.nf : L.n;
+    int64_t g = (m + kBlock - 1) / kBlock;
+    g = g > 8192 ? 8192 : (g < 1 ? 1 : g);
+    k_coeff_grad<<<(unsigned)g, kBlock, 0, st>>>(L.n, L.nf, L.own, L.nb, lam, x, gd, gu, gl);
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace ldu

@@ -39,12 +39,18 @@ def tie_key(i, j):
     return splitmix64_out((lo << 32) | hi)
 
 
-def greedy_matching(n, owner, neighbour, upper, lower):
+def strength2(owner, neighbour, upper, lower, diag):
+    """Squared coupling strength of each face relative to the diagonals."""
+    s = 0.5 * (np.abs(upper) + np.abs(lower))
+    return (s * s) / (np.abs(diag[owner]) * np.abs(diag[neighbour]))
+
+
+def greedy_matching(n, owner, neighbour, upper, lower, diag):
     """Sequential greedy matching: scan edges by (weight, tie key) descending
     and take an edge when both ends are free.  With a strict total order on
     edges this is the unique fixed point of repeated locally-dominant
     (handshake) matching rounds."""
-    w = 0.5 * (np.abs(upper) + np.abs(lower))
+    w = strength2(owner, neighbour, upper, lower, diag)
     keys = [(-w[f], -tie_key(int(owner[f]), int(neighbour[f])), f)
             for f in range(owner.size)]
     keys.sort()

@@ -1,0 +1,348 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: integer/addressing results bit-exact; Amul, Tmul, FP32 Amul and the
+Galerkin hierarchy bit-exact (same rounding sequence as the oracle's face
+loops); FP64 solves: equal iteration counts, residual histories within 1e-9
+relative, solutions within 1e-10 relative; the true residual of every GPU
+solution is recomputed by the oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from meshgen import box_case, config_case, random_order, relabel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lib():
+    from paper_2512_22215_amd import LduMatrix
+    return LduMatrix
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _perm(c, seed):
+    return relabel(c, random_order(c.n_cells, np.random.default_rng(seed)))
+
+
+def _cases():
+    return {
+        "c1": config_case("c1"),
+        "ragged": _perm(box_case(37, 29, 11, coeff="lognormal", dirichlet_x0=1.0, seed=3), 4),
+        "nonsym": _perm(box_case(13, 9, 7, coeff="lognormal", nonsym=0.6, seed=5), 6),
+        "tiny": box_case(3, 2, 1, coeff="lognormal", dirichlet_x0=1.0, seed=7),
+        "single": box_case(1, 1, 1, coeff="uniform", dirichlet_x0=1.0),
+    }
+
+
+CASES = _cases()
+
+
+def hist_close(h, ref, rel=1e-9):
+    """Residual histories agree to rel, above the FP64 noise floor of a
+    recomputed residual ||b - A x|| / ||b|| (about 1e-15 for these systems:
+    n-term sums of O(||A|| ||x||) products, rounded at 2^-53)."""
+    h = np.asarray(h)
+    return h.shape == ref.shape and bool(np.all(np.abs(h - ref) <= rel * ref + 1e-15))
+
+
+def true_res(c, x):
+    A = O.Ldu.from_case(c)
+    b = c.rhs[0]
+    return np.linalg.norm(b - O.amul(A, x)) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_amul_tmul_bit_exact(name):
+    c = CASES[name]
+    m = _lib().from_case(c)
+    A = O.Ldu.from_case(c)
+    x = np.random.default_rng(1).standard_normal(c.n_cells)
+    y = m.amul(_t(x)).cpu().numpy()
+    yt = m.tmul(_t(x)).cpu().numpy()
+    assert np.array_equal(y, O.amul(A, x))
+    assert np.array_equal(yt, O.tmul(A, x))
+    x32 = x.astype(np.float32)
+    y32 = m.amul_f32(_t(x32)).cpu().numpy()
+    assert np.array_equal(y32, O.amul_f32(A, x32))
+
+
+def test_create_rejects_bad_input():
+    from paper_2512_22215_amd import LduError
+    c = CASES["tiny"]
+    LduMatrix = _lib()
+    bad = c.neighbour.copy()
+    bad[0] = c.owner[0]
+    with pytest.raises(LduError) as e:
+        LduMatrix(c.n_cells, c.owner, bad, c.diag, c.upper, c.lower)
+    assert e.value.code == -2
+    unsorted = np.ascontiguousarray(c.owner[::-1]), np.ascontiguousarray(c.neighbour[::-1])
+    with pytest.raises(LduError) as e:
+        LduMatrix(c.n_cells, unsorted[0], unsorted[1], c.diag, c.upper, c.lower)
+    assert e.value.code == -2
+    d = c.diag.copy()
+    d[1] = np.nan
+    with pytest.raises(LduError) as e:
+        LduMatrix(c.n_cells, c.owner, c.neighbour, d, c.upper, c.lower)
+    assert e.value.code == -3
+
+
+def test_pcg_c1_matches_oracle_and_golden():
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "oracle_c1.json")))
+    c = CASES["c1"]
+    m = _lib().from_case(c)
+    x, st = m.pcg(_t(c.rhs[0]), rel_tol=1e-8, history=1000)
+    ref = O.pcg(O.Ldu.from_case(c), c.rhs[0], tol=1e-8)
+    xg = x.cpu().numpy()
+    assert st.converged and st.iterations == ref.iterations == gold["pcg"]["iterations"]
+    assert hist_close(st.history, ref.history)
+    assert true_res(c, xg) <= 1e-8
+    assert np.linalg.norm(xg - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    p = c.meta["p_exact"]
+    assert np.linalg.norm(xg - p) <= 5e-5 * np.linalg.norm(p)
+
+
+@pytest.mark.parametrize("name", ["ragged", "tiny", "single"])
+def test_pcg_matches_oracle(name):
+    c = CASES[name]
+    m = _lib().from_case(c)
+    x, st = m.pcg(_t(c.rhs[0]), rel_tol=1e-10, history=5000)
+    ref = O.pcg(O.Ldu.from_case(c), c.rhs[0], tol=1e-10)
+    xg = x.cpu().numpy()
+    assert st.converged and st.iterations == ref.iterations
+    assert np.linalg.norm(xg - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    assert true_res(c, xg) <= 1e-10
+
+
+def test_pcg_edge_cases():
+    c = CASES["ragged"]
+    m = _lib().from_case(c)
+    x, st = m.pcg(torch.zeros(c.n_cells, dtype=torch.float64, device="cuda"),
+                  x0=torch.ones(c.n_cells, dtype=torch.float64, device="cuda"))
+    assert st.status == 0 and st.iterations == 0 and float(x.abs().max()) == 0.0
+    x, st = m.pcg(_t(c.rhs[0]), max_iter=1)
+    assert st.status == 1 and st.iterations == 1 and not st.converged
+    ref = O.pcg(O.Ldu.from_case(c), c.rhs[0], max_iter=1)
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+
+
+def _gamg_case(name):
+    if name == "c2s":
+        return config_case("c2", n=24)
+    if name == "c3p":
+        return config_case("c3", nxy=24)  # the 200-layer graded column, 24 x 24 wide
+    if name == "c5s":
+        return config_case("c5", n=36)
+    if name == "c3s":
+        # the graded, jittered workload at 40^3
+        from meshgen.boxes import _rng, assemble_diag, box_faces, LduCase
+        n = 40
+        dx = 1.0 / n
+        dz = np.minimum((dx / 100.0) * 1.05 ** np.arange(n), dx)
+        own, nb, ax = box_faces(n, n, n)
+        kz = own // (n * n)
+        a = np.where(ax < 2, dz[kz], dx * dx / (0.5 * (dz[kz] + dz[np.minimum(kz + 1, n - 1)])))
+        a = a * _rng(3, 2).uniform(0.95, 1.05, own.size)
+        ab = np.zeros(n ** 3)
+        ab[np.arange(n ** 3) // (n * n) == n - 1] = dx * dx / (0.5 * dz[n - 1])
+        d = assemble_diag(n ** 3, own, nb, a, a, ab)
+        return LduCase("c3s", n ** 3, own, nb, d, a, a.copy(),
+                       [_rng(3, 3).standard_normal(n ** 3)], False)
+    return CASES[name]
+
+
+@pytest.mark.parametrize("name", ["c2s", "c3s", "ragged", "c1", "nonsym"])
+def test_gamg_hierarchy_bit_exact(name):
+    c = _gamg_case(name)
+    m = _lib().from_case(c)
+    m.gamg_setup()
+    g = O.Gamg(O.Ldu.from_case(c))
+    assert m.n_levels() == g.n_levels
+    for l in range(g.n_levels):
+        got = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in m.level(l).items()}
+        ref = g.level(l)
+        assert got["n"] == ref.n and got["nf"] == ref.nf
+        if ref.agg is not None:
+            assert np.array_equal(got["agg"], ref.agg)
+        for k, rv in (("owner", ref.owner), ("neighbour", ref.neighbour), ("diag", ref.diag),
+                      ("upper", ref.upper), ("lower", ref.lower)):
+            assert np.array_equal(got[k], rv), (l, k)
+
+
+@pytest.mark.parametrize("name", ["c2s", "c3s", "ragged"])
+def test_vcycle_matches_oracle(name):
+    c = _gamg_case(name)
+    m = _lib().from_case(c)
+    g = O.Gamg(O.Ldu.from_case(c))
+    r = np.random.default_rng(9).standard_normal(c.n_cells)
+    if c.singular:
+        r -= r.mean()
+    e = m.vcycle(_t(r)).cpu().numpy()
+    ref = g.vcycle(r)
+    assert np.linalg.norm(e - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name", ["c2s", "c5s", "ragged"])
+def test_gamg_solve_matches_oracle(name):
+    c = _gamg_case(name)
+    m = _lib().from_case(c)
+    x, st = m.gamg(_t(c.rhs[0]), rel_tol=1e-8, history=300)
+    ref = O.Gamg(O.Ldu.from_case(c)).solve(c.rhs[0], tol=1e-8)
+    xg = x.cpu().numpy()
+    assert st.converged and st.iterations == ref.iterations
+    assert hist_close(st.history, ref.history)
+    if c.singular:
+        xg = xg - xg.mean()
+        xr = ref.x - ref.x.mean()
+    else:
+        xr = ref.x
+    assert np.linalg.norm(xg - xr) <= 1e-10 * np.linalg.norm(xr)
+    assert true_res(c, x.cpu().numpy()) <= 1e-8
+
+
+@pytest.mark.parametrize("solver", ["pcg", "gamg"])
+def test_mixed_refines_to_fp64(solver):
+    c = _gamg_case("c5s") if solver == "gamg" else CASES["ragged"]
+    m = _lib().from_case(c)
+    A = O.Ldu.from_case(c)
+    if solver == "pcg":
+        x, st = m.pcg(_t(c.rhs[0]), rel_tol=1e-12, precision="mixed")
+        ref = O.pcg(A, c.rhs[0], tol=1e-12)
+    else:
+        x, st = m.gamg(_t(c.rhs[0]), rel_tol=1e-12, precision="mixed")
+        ref = O.Gamg(A).solve(c.rhs[0], tol=1e-12)
+    xg = x.cpu().numpy()
+    assert st.converged and true_res(c, xg) <= 1e-12
+    assert np.linalg.norm(xg - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+def test_adjoint_and_gradients_match_oracle():
+    c = CASES["nonsym"]
+    m = _lib().from_case(c)
+    A = O.Ldu.from_case(c)
+    g = np.random.default_rng(3).standard_normal(c.n_cells)
+    lam, st = m.adjoint(_t(g), use_gamg=True, rel_tol=1e-12)
+    gg = O.Gamg(A)
+    ref = gg.solve(g, tol=1e-12, transpose=True)
+    assert st.converged and st.iterations == ref.iterations
+    lg = lam.cpu().numpy()
+    assert np.linalg.norm(lg - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    x = np.random.default_rng(4).standard_normal(c.n_cells)
+    gd, gu, gl = (t.cpu().numpy() for t in m.coeff_grad(lam, _t(x)))
+    rd, ru, rl = O.coeff_grad(A, lg, x)
+    assert np.array_equal(gd, rd) and np.array_equal(gu, ru) and np.array_equal(gl, rl)
+
+
+def test_deterministic_bitwise():
+    c = _gamg_case("c2s")
+    m = _lib().from_case(c)
+    x1, _ = m.gamg(_t(c.rhs[0]))
+    x2, _ = m.gamg(_t(c.rhs[0]))
+    m2 = _lib().from_case(c)
+    x3, _ = m2.gamg(_t(c.rhs[0]))
+    assert torch.equal(x1, x2) and torch.equal(x1, x3)
+    p1, _ = m.pcg(_t(c.rhs[0]))
+    p2, _ = m2.pcg(_t(c.rhs[0]))
+    assert torch.equal(p1, p2)
+
+
+@pytest.mark.parametrize("name", ["c3p", "c2s", "ragged"])
+def test_pcg_gamg_matches_oracle(name):
+    c = _gamg_case(name)
+    m = _lib().from_case(c)
+    x, st = m.pcg(_t(c.rhs[0]), precond=2, rel_tol=1e-8, history=500)
+    ref = O.Gamg(O.Ldu.from_case(c)).pcg(c.rhs[0], tol=1e-8)
+    xg = x.cpu().numpy()
+    assert st.converged and st.iterations == ref.iterations
+    assert hist_close(st.history, ref.history, 1e-8)
+    if c.singular:
+        xg, xr = xg - xg.mean(), ref.x - ref.x.mean()
+    else:
+        xr = ref.x
+    assert np.linalg.norm(xg - xr) <= 1e-9 * np.linalg.norm(xr)
+    assert true_res(c, x.cpu().numpy()) <= 1e-8
+
+
+def test_set_coeffs_recomputes_cached_hierarchy():
+    from meshgen import assemble_diag
+    c = _gamg_case("c5s")
+    m = _lib().from_case(c)
+    m.gamg_setup()
+    a2 = c.upper * np.exp(0.3 * np.random.default_rng(5).standard_normal(c.n_faces))
+    d2 = assemble_diag(c.n_cells, c.owner, c.neighbour, a2, a2, c.meta["a_boundary"])
+    m.set_coeffs(_t(d2), _t(a2), _t(a2))
+    g = O.Gamg(O.Ldu.from_case(c))
+    g.set_values(d2, a2, a2)
+    assert m.n_levels() == g.n_levels
+    for l in range(g.n_levels):
+        got = m.level(l)
+        ref = g.level(l)
+        for k, rv in (("diag", ref.diag), ("upper", ref.upper), ("lower", ref.lower)):
+            assert np.array_equal(got[k].cpu().numpy(), rv), (l, k)
+    A2 = O.Ldu(c.n_cells, c.owner, c.neighbour, d2, a2, a2)
+    x = np.random.default_rng(6).standard_normal(c.n_cells)
+    assert np.array_equal(m.amul(_t(x)).cpu().numpy(), O.amul(A2, x))
+    xs, st = m.gamg(_t(c.rhs[0]))
+    ref = g.solve(c.rhs[0])
+    assert st.iterations == ref.iterations
+    assert np.linalg.norm(xs.cpu().numpy() - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+def test_autograd_matches_oracle_and_finite_differences():
+    from meshgen import assemble_diag
+    from paper_2512_22215_amd import ldu_solve
+    c = box_case(9, 8, 7, coeff="lognormal", dirichlet_x0=2.0, seed=11)
+    ab = np.where(np.arange(c.n_cells) % 9 == 0, 2.0, 0.0)
+    xt = np.random.default_rng(12).standard_normal(c.n_cells)
+    m = _lib().from_case(c)
+    a = _t(c.upper).requires_grad_(True)
+    b = _t(c.rhs[0]).requires_grad_(True)
+    own = torch.from_numpy(c.owner.astype(np.int64)).cuda()
+    nb = torch.from_numpy(c.neighbour.astype(np.int64)).cuda()
+
+    def assemble(a):
+        d = -(torch.zeros(c.n_cells, dtype=torch.float64, device="cuda")
+              .index_add(0, own, a).index_add(0, nb, a)) - _t(ab)
+        return d
+
+    x = ldu_solve(assemble(a), a, a, b, m, "pcg", rel_tol=1e-13)
+    loss = 0.5 * torch.sum((x - _t(xt)) ** 2)
+    loss.backward()
+    ga = a.grad.cpu().numpy()
+    xn = x.detach().cpu().numpy()
+    # oracle adjoint gradient for the symmetric face coefficient
+    A = O.Ldu(c.n_cells, c.owner, c.neighbour, assemble_diag(c.n_cells, c.owner, c.neighbour,
+                                                             c.upper, c.upper, ab),
+              c.upper, c.upper)
+    lam = O.pcg(A, xn - xt, tol=1e-13, transpose=True).x
+    closed = (lam[c.owner] - lam[c.neighbour]) * (xn[c.owner] - xn[c.neighbour])
+    assert np.allclose(ga, closed, rtol=1e-8, atol=1e-10 * np.abs(closed).max())
+    assert np.linalg.norm(b.grad.cpu().numpy() - lam) <= 1e-9 * np.linalg.norm(lam)
+
+    from tests.dense_ref import dense
+
+    def L(av):
+        # dense LU: loss evaluations accurate to ~1e-16 relative, so the
+        # central difference resolves the gradient to ~1e-7
+        d = assemble_diag(c.n_cells, c.owner, c.neighbour, av, av, ab)
+        xx = np.linalg.solve(dense(c.n_cells, c.owner, c.neighbour, d, av, av), c.rhs[0])
+        return 0.5 * np.sum((xx - xt) ** 2)
+
+    # relative step 1e-4: truncation O(h^2) and roundoff (eps L / h) both stay
+    # below 1e-7 of the gradient here; at 1e-6 the roundoff of L alone
+    # reaches 5e-5 on faces with small gradients
+    for f in np.random.default_rng(13).choice(c.n_faces, 5, replace=False):
+        h = 1e-4 * c.upper[f]
+        ap = c.upper.copy(); ap[f] += h
+        am = c.upper.copy(); am[f] -= h
+        fd = (L(ap) - L(am)) / (2 * h)
+        assert abs(fd - ga[f]) <= 1e-5 * max(abs(ga[f]), 1e-3 * np.abs(ga).max())

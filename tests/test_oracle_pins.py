@@ -14,7 +14,8 @@ from meshgen import (assemble_diag, box_case, box_faces, config_case,
                      random_order, relabel)
 from meshgen.boxes import LduCase, c3_spacing
 from tests.dense_ref import (closed_form_1d, dense, dense_case,
-                             greedy_matching, prolongation, tie_key)
+                             greedy_matching, prolongation, strength2,
+                             tie_key)
 
 
 def _perm_case(case, seed):
@@ -290,7 +291,7 @@ def test_matching_equals_greedy(idx):
     g = O.Gamg(O.Ldu.from_case(c), n_coarsest=2, max_levels=2,
                match_rounds=100000)
     L = g.level(0)
-    ref = greedy_matching(c.n_cells, c.owner, c.neighbour, c.upper, c.lower)
+    ref = greedy_matching(c.n_cells, c.owner, c.neighbour, c.upper, c.lower, c.diag)
     assert np.array_equal(L.partner, ref)
 
 
@@ -302,9 +303,10 @@ def test_leftovers_and_numbering(idx):
     L = g.level(0)
     n = c.n_cells
     nbrs = [[] for _ in range(n)]
+    ws = strength2(c.owner, c.neighbour, c.upper, c.lower, c.diag)
     for f in range(c.n_faces):
         i, j = int(c.owner[f]), int(c.neighbour[f])
-        w = 0.5 * (abs(c.upper[f]) + abs(c.lower[f]))
+        w = ws[f]
         nbrs[i].append((j, w))
         nbrs[j].append((i, w))
     p = L.partner
@@ -534,3 +536,46 @@ def test_adjoint_of_symmetric_is_forward():
     f = O.pcg(A, c.rhs[0], tol=1e-12)
     t = O.pcg(A, c.rhs[0], tol=1e-12, transpose=True)
     assert np.array_equal(f.x, t.x)
+
+
+# ---------------------------------------------------------------- CG + V-cycle
+
+def test_vcycle_pcg_exact_preconditioner_one_iteration():
+    """With a single level the V-cycle is the coarsest solve (CG to 1e-10),
+    i.e. nearly A^-1, so the preconditioned CG stops after one iteration."""
+    c = box_case(4, 3, 3, coeff="lognormal", dirichlet_x0=1.0, seed=40)
+    g = O.Gamg(O.Ldu.from_case(c), n_coarsest=1000)
+    assert g.n_levels == 1
+    r = g.pcg(c.rhs[0], tol=1e-8)
+    assert r.status == O.OK and r.iterations == 1
+
+
+def test_vcycle_pcg_matches_dense_and_beats_diagonal():
+    c = _perm_case(box_case(9, 8, 7, coeff="lognormal", sigma=1.0,
+                            dirichlet_x0=1.0, seed=41), 42)
+    A = O.Ldu.from_case(c)
+    g = O.Gamg(A, n_coarsest=10)
+    r = g.pcg(c.rhs[0], tol=1e-12)
+    xd = np.linalg.solve(dense_case(c), c.rhs[0])
+    assert r.status == O.OK
+    assert np.linalg.norm(r.x - xd) <= 1e-10 * np.linalg.norm(xd)
+    assert r.iterations < O.pcg(A, c.rhs[0], tol=1e-12).iterations / 2
+
+
+def test_set_values_equals_fresh_galerkin_on_same_aggregation():
+    c = box_case(7, 6, 5, coeff="lognormal", dirichlet_x0=1.0, seed=43)
+    g = O.Gamg(O.Ldu.from_case(c), n_coarsest=10)
+    a2 = c.upper * np.exp(0.3 * np.random.default_rng(44).standard_normal(c.n_faces))
+    d2 = assemble_diag(c.n_cells, c.owner, c.neighbour, a2, a2,
+                       np.where(np.arange(c.n_cells) % 7 == 0, 1.0, 0.0))
+    aggs = [g.level(l).agg for l in range(g.n_levels - 1)]
+    g.set_values(d2, a2, a2)
+    Af = dense(c.n_cells, c.owner, c.neighbour, d2, a2, a2)
+    for l in range(g.n_levels - 1):
+        F, Cl = g.level(l), g.level(l + 1)
+        assert np.array_equal(F.agg, aggs[l])
+        P = prolongation(F.agg, Cl.n)
+        Ac = dense(Cl.n, Cl.owner, Cl.neighbour, Cl.diag, Cl.upper, Cl.lower)
+        ref = P.T @ Af @ P
+        assert np.allclose(Ac, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+        Af = Ac

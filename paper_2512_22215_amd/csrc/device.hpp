@@ -7,8 +7,8 @@
 //   +-nx*ny neighbour band of a cell is then read from the L2 that fetched it
 //   instead of the L2 of another XCD.
 // - deterministic reductions: a fixed butterfly inside the wavefront, a fixed
-//   order across the 4 wavefronts of a block, one partial per block, and the
-//   last block to arrive (integer ticket) sums the partials in a fixed order.
+//   order across the 4 wavefronts of a block, one partial per block, and a
+//   one-block finalize kernel that sums the partials in a fixed order.
 //   Results are bitwise reproducible run to run; no floating-point atomics.
 // - sell_row: one row of a sliced-ELLPACK product, diagonal first and then
 //   the entries in column order, each product rounded before its addition
@@ -70,42 +70,43 @@ __device__ __forceinline__ void block_reduce(double (&v)[K]) {
     }
 }
 
-// grid-wide reduction of K per-thread values (the last M by max); the last
-// block to arrive calls epi(total) in its thread 0.  partials holds
-// K * kMaxGrid doubles.  Every block of the grid must call this exactly once.
-template <int K, int M = 0, class Epi>
-__device__ __forceinline__ void grid_reduce(double (&v)[K], double *partials,
-                                            DevScalars *ds, Epi &&epi) {
-    __shared__ int am_last;
+// grid-wide reductions in two launches: every block of the producer kernel
+// stores its block total in partials[k * kMaxGrid + block] (plain stores; the
+// kernel boundary makes them visible), then k_finalize, one block, sums the
+// partials in a fixed order and runs the epilogue.  A single-kernel variant
+// needs an agent-scope release per block, which on this chip writes back L2
+// and cost ~60% of a streaming kernel's time.
+template <int K, int M = 0>
+__device__ __forceinline__ void block_partials(double (&v)[K], double *partials) {
     block_reduce<K, M>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            __hip_atomic_store(&partials[k * kMaxGrid + blockIdx.x], v[k],
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned t = atomicAdd(&ds->ticket, 1u);
-        am_last = (t == gridDim.x - 1);
+        for (int k = 0; k < K; ++k) partials[k * kMaxGrid + blockIdx.x] = v[k];
     }
-    __syncthreads();
-    if (!am_last) return;
-    __threadfence();
+}
+
+template <int K, int M, class Epi>
+__global__ void __launch_bounds__(kBlock)
+k_finalize(const double *__restrict__ partials, int nblocks, DevScalars *ds, Epi epi) {
+    if (!epi.active(ds)) return;
     double s[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const double p = __hip_atomic_load(&partials[k * kMaxGrid + b], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+            const double p = partials[k * kMaxGrid + b];
             s[k] = (k >= K - M) ? fmax(s[k], p) : s[k] + p;
         }
     }
     block_reduce<K, M>(s);
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(&ds->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        epi(s);
-    }
+    if (threadIdx.x == 0) epi(s, ds);
+}
+
+template <int K, int M = 0, class Epi>
+inline void launch_finalize(double *partials, int nblocks, DevScalars *ds, const Epi &epi,
+                            hipStream_t st) {
+    k_finalize<K, M, Epi><<<1, kBlock, 0, st>>>(partials, nblocks, ds, epi);
 }
 
 // x accessors for the product kernels

@@ -478,7 +478,7 @@ k_vc_restrict(int32_t nc, const int32_t *__restrict__ start, const int32_t *__re
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_scale(SellView<T> A, const T *__restrict__ ec, const int32_t *__restrict__ agg,
-           const T *__restrict__ t, double *partials, DevScalars *ds) {
+           const T *__restrict__ t, double *partials, const DevScalars *ds) {
     if (ds->done) return;
     const int lane = threadIdx.x & 63;
     double acc[2] = {0.0, 0.0};
@@ -491,10 +491,15 @@ k_vc_scale(SellView<T> A, const T *__restrict__ ec, const int32_t *__restrict__ 
             acc[1] += (double)ci * (double)ac;
         }
     });
-    grid_reduce<2>(acc, partials, ds, [&](const double *v) {
-        ds->s = (isfinite(v[1]) && fabs(v[1]) > 1e-300) ? v[0] / v[1] : 1.0;
-    });
+    block_partials<2>(acc, partials);
 }
+
+struct EpiScale {
+    __device__ bool active(const DevScalars *ds) const { return !ds->done; }
+    __device__ void operator()(const double *v, DevScalars *ds) const {
+        ds->s = (isfinite(v[1]) && fabs(v[1]) > 1e-300) ? v[0] / v[1] : 1.0;
+    }
+};
 
 // e += s c
 template <typename T>
@@ -685,8 +690,10 @@ static T *vcycle(const VCtx &c, size_t l, const T *r) {
     T *rc = lvec<T>(C, 0);
     k_vc_restrict<T><<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, t, rc, h->dev);
     const T *ec = vcycle<T>(c, l + 1, rc);
-    if (c.o->scale_correction)
+    if (c.o->scale_correction) {
         k_vc_scale<T><<<G, kBlock, 0, st>>>(A, ec, L.agg, t, h->partials, h->dev);
+        launch_finalize<2>(h->partials, G, h->dev, EpiScale{}, st);
+    }
     k_vc_correct<T><<<G, kBlock, 0, st>>>(L.n, S, ec, L.agg, e, c.o->scale_correction, h->dev);
     for (int k = 0; k < c.o->n_post; ++k) {
         k_vc_jacobi<T><<<G, kBlock, 0, st>>>(A, r, e, e2, omega, h->dev);
@@ -787,7 +794,7 @@ int gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_gamg_opts &o, bool
 // p = z; rho = r.z
 __global__ void __launch_bounds__(kBlock)
 k_pg_start(int32_t n, int64_t S, const double *__restrict__ r, const double *__restrict__ z,
-           double *__restrict__ p, double *partials, DevScalars *ds) {
+           double *__restrict__ p, double *partials, const DevScalars *ds) {
     if (ds->done) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
@@ -799,14 +806,19 @@ k_pg_start(int32_t n, int64_t S, const double *__restrict__ r, const double *__r
             acc[0] += r[i] * zi;
         }
     });
-    grid_reduce<1>(acc, partials, ds, [&](const double *t) { ds->rho = t[0]; });
+    block_partials<1>(acc, partials);
 }
 
-// x += alpha p; r -= alpha q; ||r||^2; convergence test
+struct EpiRho {
+    __device__ bool active(const DevScalars *ds) const { return !ds->done; }
+    __device__ void operator()(const double *t, DevScalars *ds) const { ds->rho = t[0]; }
+};
+
+// x += alpha p; r -= alpha q; ||r||^2
 __global__ void __launch_bounds__(kBlock)
 k_pg_update(int32_t n, int64_t S, double *__restrict__ x, double *__restrict__ r,
             const double *__restrict__ p, const double *__restrict__ q, double *partials,
-            DevScalars *ds, double *hist) {
+            const DevScalars *ds) {
     if (ds->done) return;
     const double alpha = ds->alpha;
     const int lane = threadIdx.x & 63;
@@ -820,28 +832,13 @@ k_pg_update(int32_t n, int64_t S, double *__restrict__ x, double *__restrict__ r
             acc[0] += ri * ri;
         }
     });
-    grid_reduce<1>(acc, partials, ds, [&](const double *t) {
-        const int it = ds->iters + 1;
-        ds->iters = it;
-        ds->rr = t[0];
-        const double res = sqrt(t[0]) / ds->bnorm;
-        ds->res = res;
-        if (hist) hist[it] = res;
-        if (!isfinite(res)) {
-            ds->status = LDU_ERR_NAN;
-            ds->done = kFailed;
-        } else if (res <= ds->tol) {
-            ds->done = kConverged;
-        } else if (it >= ds->max_iter) {
-            ds->done = kMaxIter;
-        }
-    });
+    block_partials<1>(acc, partials);
 }
 
 // rho' = r.z; beta = rho'/rho
 __global__ void __launch_bounds__(kBlock)
 k_pg_rz(int32_t n, int64_t S, const double *__restrict__ r, const double *__restrict__ z,
-        double *partials, DevScalars *ds) {
+        double *partials, const DevScalars *ds) {
     if (ds->done) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
@@ -849,11 +846,16 @@ k_pg_rz(int32_t n, int64_t S, const double *__restrict__ r, const double *__rest
         const int64_t i = s * kWave + lane;
         if (i < n) acc[0] += r[i] * z[i];
     });
-    grid_reduce<1>(acc, partials, ds, [&](const double *t) {
+    block_partials<1>(acc, partials);
+}
+
+struct EpiBeta {
+    __device__ bool active(const DevScalars *ds) const { return !ds->done; }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
         ds->beta = t[0] / ds->rho;
         ds->rho = t[0];
-    });
-}
+    }
+};
 
 // p = z + beta p
 __global__ void __launch_bounds__(kBlock)
@@ -903,13 +905,16 @@ int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, b
     while (res > o.rel_tol) {
         const double *z = vcycle<double>(c, 0, h->r);
         k_pg_start<<<G, kBlock, 0, st>>>(n, S, h->r, z, h->p, h->partials, h->dev);
+        launch_finalize<1>(h->partials, G, h->dev, EpiRho{}, st);
         for (;;) {
             for (int k = 0; k < every; ++k) {
                 launch_pcg_q(h, A, h->p, h->q, G, st);
                 k_pg_update<<<G, kBlock, 0, st>>>(n, S, x, h->r, h->p, h->q, h->partials,
-                                                  h->dev, h->hist);
+                                                  h->dev);
+                launch_converge(h, G, false, st);
                 z = vcycle<double>(c, 0, h->r);
                 k_pg_rz<<<G, kBlock, 0, st>>>(n, S, h->r, z, h->partials, h->dev);
+                launch_finalize<1>(h->partials, G, h->dev, EpiBeta{}, st);
                 k_pg_p<<<G, kBlock, 0, st>>>(n, S, z, h->p, h->dev);
             }
             HIP_CHECK(hipGetLastError());

@@ -89,9 +89,9 @@ enum { kResPlain = 0, kResCycle = 1 };
 template <bool P, bool MAXABS>
 __global__ void __launch_bounds__(kBlock)
 k_residual(SellView<double> A, const double *__restrict__ b, const double *__restrict__ x,
-           double *__restrict__ r, double *__restrict__ p, int precond, int mode,
-           int write_hist, double *partials, DevScalars *ds, double *hist) {
-    if (mode == kResCycle && ds->done) return;
+           double *__restrict__ r, double *__restrict__ p, int precond, int gated,
+           double *partials, const DevScalars *ds) {
+    if (gated && ds->done) return;
     const int lane = threadIdx.x & 63;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // rr, bb, rho, maxabs
     for_each_slice(A.nslices, [&](int64_t s) {
@@ -110,12 +110,23 @@ k_residual(SellView<double> A, const double *__restrict__ b, const double *__res
             if (MAXABS) acc[3] = fmax(acc[3], fabs(ri));
         }
     });
-    grid_reduce<4, 1>(acc, partials, ds, [&](const double *t) {
+    block_partials<4, 1>(acc, partials);
+}
+
+// epilogue of the residual: scalars, history entry and, for the outer loop
+// of GAMG and of the refinement (kResCycle), the convergence decision
+struct EpiResidual {
+    int mode, write_hist, has_p;
+    double *hist;
+    __device__ bool active(const DevScalars *ds) const {
+        return mode != kResCycle || !ds->done;
+    }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
         ds->rr = t[0];
         ds->bb = t[1];
         ds->bnorm = sqrt(t[1]);
         ds->maxabs = t[3];
-        if (P) ds->rho = t[2];
+        if (has_p) ds->rho = t[2];
         const double res = ds->bnorm > 0.0 ? sqrt(t[0]) / ds->bnorm : 0.0;
         ds->res = res;
         const int it = ds->iters;
@@ -132,35 +143,39 @@ k_residual(SellView<double> A, const double *__restrict__ b, const double *__res
                 ds->iters = it + 1;
             }
         }
-    });
+    }
+};
+
+template <bool P, bool MAXABS>
+static void launch_residual(ldu_t *h, const SellView<double> &A, const double *b, const double *x,
+                            double *r, double *p, int precond, int mode, bool write_hist,
+                            hipStream_t st) {
+    const int G = stream_grid_slices(A.nslices);
+    k_residual<P, MAXABS><<<G, kBlock, 0, st>>>(A, b, x, r, p, precond, mode == kResCycle,
+                                                h->partials, h->dev);
+    launch_finalize<4, 1>(h->partials, G, h->dev,
+                          EpiResidual{mode, write_hist ? 1 : 0, P ? 1 : 0, h->hist}, st);
+    HIP_CHECK(hipGetLastError());
 }
 
 void launch_residual_cycle(ldu_t *h, const SellView<double> &A, const double *b,
                            const double *x, double *r, bool maxabs, int grid,
                            hipStream_t st) {
-    if (maxabs)
-        k_residual<false, true><<<grid, kBlock, 0, st>>>(A, b, x, r, nullptr, 0, kResCycle, 1,
-                                                         h->partials, h->dev, h->hist);
-    else
-        k_residual<false, false><<<grid, kBlock, 0, st>>>(A, b, x, r, nullptr, 0, kResCycle, 1,
-                                                          h->partials, h->dev, h->hist);
-    HIP_CHECK(hipGetLastError());
+    (void)grid;
+    if (maxabs) launch_residual<false, true>(h, A, b, x, r, nullptr, 0, kResCycle, true, st);
+    else launch_residual<false, false>(h, A, b, x, r, nullptr, 0, kResCycle, true, st);
 }
 
 void launch_residual_plain(ldu_t *h, const SellView<double> &A, const double *b,
                            const double *x, double *r, bool write_hist, int grid,
                            hipStream_t st) {
-    k_residual<false, false><<<grid, kBlock, 0, st>>>(A, b, x, r, nullptr, 0, kResPlain,
-                                                      write_hist ? 1 : 0, h->partials, h->dev,
-                                                      h->hist);
-    HIP_CHECK(hipGetLastError());
+    (void)grid;
+    launch_residual<false, false>(h, A, b, x, r, nullptr, 0, kResPlain, write_hist, st);
 }
 
 double residual_norm(ldu_t *h, const Level &L, bool tr, const double *b, const double *x,
                      double *r_out, hipStream_t st) {
-    k_residual<false, false><<<stream_grid_slices(L.A.nslices), kBlock, 0, st>>>(
-        L.A.view(tr), b, x, r_out, nullptr, 0, kResPlain, 0, h->partials, h->dev, nullptr);
-    HIP_CHECK(hipGetLastError());
+    launch_residual<false, false>(h, L.A.view(tr), b, x, r_out, nullptr, 0, kResPlain, false, st);
     read_scalars(h, st);
     return h->host->res;
 }
@@ -169,7 +184,7 @@ double residual_norm(ldu_t *h, const Level &L, bool tr, const double *b, const d
 // q = A p and p.q -> alpha = rho / p.q
 __global__ void __launch_bounds__(kBlock)
 k_pcg_q(SellView<double> A, const double *__restrict__ p, double *__restrict__ q,
-        double *partials, DevScalars *ds) {
+        double *partials, const DevScalars *ds) {
     if (ds->done) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
@@ -181,7 +196,12 @@ k_pcg_q(SellView<double> A, const double *__restrict__ p, double *__restrict__ q
             acc[0] += p[i] * qi;
         }
     });
-    grid_reduce<1>(acc, partials, ds, [&](const double *t) {
+    block_partials<1>(acc, partials);
+}
+
+struct EpiAlpha {
+    __device__ bool active(const DevScalars *ds) const { return !ds->done; }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
         const double pq = t[0];
         ds->pq = pq;
         if (!isfinite(pq) || fabs(pq) <= 1e-300) {
@@ -190,19 +210,20 @@ k_pcg_q(SellView<double> A, const double *__restrict__ p, double *__restrict__ q
         } else {
             ds->alpha = ds->rho / pq;
         }
-    });
-}
+    }
+};
 
 void launch_pcg_q(ldu_t *h, const SellView<double> &A, const double *p, double *q, int grid,
                   hipStream_t st) {
     k_pcg_q<<<grid, kBlock, 0, st>>>(A, p, q, h->partials, h->dev);
+    launch_finalize<1>(h->partials, grid, h->dev, EpiAlpha{}, st);
 }
 
-// x += alpha p; r -= alpha q; ||r||^2 and r.D^-1 r; convergence test
+// x += alpha p; r -= alpha q; ||r||^2 and r.D^-1 r
 __global__ void __launch_bounds__(kBlock)
 k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restrict__ x,
              double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ q,
-             int precond, double *partials, DevScalars *ds, double *hist) {
+             int precond, double *partials, const DevScalars *ds) {
     if (ds->done) return;
     const double alpha = ds->alpha;
     const int lane = threadIdx.x & 63;
@@ -219,7 +240,16 @@ k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restr
             acc[1] += ri * zi;
         }
     });
-    grid_reduce<2>(acc, partials, ds, [&](const double *t) {
+    block_partials<2>(acc, partials);
+}
+
+// iteration count, residual history and convergence test after the x, r
+// update; with_beta: also beta = rho'/rho from the second sum
+struct EpiConverge {
+    double *hist;
+    int with_beta;
+    __device__ bool active(const DevScalars *ds) const { return !ds->done; }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
         const int it = ds->iters + 1;
         ds->iters = it;
         ds->rr = t[0];
@@ -233,11 +263,16 @@ k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restr
             ds->done = kConverged;
         } else if (it >= ds->max_iter) {
             ds->done = kMaxIter;
-        } else {
+        } else if (with_beta) {
             ds->beta = t[1] / ds->rho;
             ds->rho = t[1];
         }
-    });
+    }
+};
+
+void launch_converge(ldu_t *h, int grid, bool with_beta, hipStream_t st) {
+    if (with_beta) launch_finalize<2>(h->partials, grid, h->dev, EpiConverge{h->hist, 1}, st);
+    else launch_finalize<1>(h->partials, grid, h->dev, EpiConverge{h->hist, 0}, st);
 }
 
 // p = D^-1 r + beta p
@@ -289,9 +324,7 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
     ensure_hist(h, o.max_iter + 2);
     fill_stats_common(stats);
     set_scalars_for_solve(h, o.rel_tol, o.max_iter, st);
-    k_residual<true, false><<<G, kBlock, 0, st>>>(A, b, x, h->r, h->p, precond, kResPlain, 1,
-                                                  h->partials, h->dev, h->hist);
-    HIP_CHECK(hipGetLastError());
+    launch_residual<true, false>(h, A, b, x, h->r, h->p, precond, kResPlain, true, st);
     read_scalars(h, st);
     DevScalars &hs = *h->host;
     if (stats) stats->initial_residual = hs.res;
@@ -313,9 +346,10 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
     while (res > o.rel_tol) {
         for (;;) {
             for (int k = 0; k < every; ++k) {
-                k_pcg_q<<<G, kBlock, 0, st>>>(A, h->p, h->q, h->partials, h->dev);
+                launch_pcg_q(h, A, h->p, h->q, G, st);
                 k_pcg_update<<<G, kBlock, 0, st>>>(n, S, A.diag, x, h->r, h->p, h->q, precond,
-                                                   h->partials, h->dev, h->hist);
+                                                   h->partials, h->dev);
+                launch_converge(h, G, true, st);
                 k_pcg_p<<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->p, precond, h->dev);
             }
             HIP_CHECK(hipGetLastError());
@@ -327,9 +361,7 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
             break;
         }
         // true residual; restart from it if the recursive one drifted
-        k_residual<true, false><<<G, kBlock, 0, st>>>(A, b, x, h->r, h->p, precond, kResPlain,
-                                                      0, h->partials, h->dev, nullptr);
-        HIP_CHECK(hipGetLastError());
+        launch_residual<true, false>(h, A, b, x, h->r, h->p, precond, kResPlain, false, st);
         read_scalars(h, st);
         res = hs.res;
         if (!std::isfinite(res)) { status = LDU_ERR_NAN; break; }
@@ -355,7 +387,7 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
 __global__ void __launch_bounds__(kBlock)
 k_mx_start(int32_t n, int64_t S, const double *__restrict__ r, const float *__restrict__ D,
            float *__restrict__ r32, float *__restrict__ d32, float *__restrict__ p32,
-           double *partials, DevScalars *ds) {
+           double *partials, const DevScalars *ds) {
     if (ds->done) return;
     const double sc = ds->maxabs;
     const int lane = threadIdx.x & 63;
@@ -372,18 +404,23 @@ k_mx_start(int32_t n, int64_t S, const double *__restrict__ r, const float *__re
             acc[1] += (double)ri * (double)zi;
         }
     });
-    grid_reduce<2>(acc, partials, ds, [&](const double *t) {
-        ds->scale = sc;
+    block_partials<2>(acc, partials);
+}
+
+struct EpiMxStart {
+    __device__ bool active(const DevScalars *ds) const { return !ds->done; }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
+        ds->scale = ds->maxabs;
         ds->r0 = sqrt(t[0]);
         ds->rho = t[1];
         ds->inner_iters = 0;
         ds->inner_done = !(ds->r0 > 0.0);
-    });
-}
+    }
+};
 
 __global__ void __launch_bounds__(kBlock)
 k_mx_q(SellView<float> A, const float *__restrict__ p, float *__restrict__ q, double *partials,
-       DevScalars *ds) {
+       const DevScalars *ds) {
     if (ds->done || ds->inner_done) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
@@ -395,20 +432,22 @@ k_mx_q(SellView<float> A, const float *__restrict__ p, float *__restrict__ q, do
             acc[0] += (double)p[i] * (double)qi;
         }
     });
-    grid_reduce<1>(acc, partials, ds, [&](const double *t) {
-        const double pq = t[0];
-        if (!isfinite(pq) || fabs(pq) <= 1e-300) {
-            ds->inner_done = 1;
-        } else {
-            ds->alpha = ds->rho / pq;
-        }
-    });
+    block_partials<1>(acc, partials);
 }
+
+struct EpiMxAlpha {
+    __device__ bool active(const DevScalars *ds) const { return !(ds->done || ds->inner_done); }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
+        const double pq = t[0];
+        if (!isfinite(pq) || fabs(pq) <= 1e-300) ds->inner_done = 1;
+        else ds->alpha = ds->rho / pq;
+    }
+};
 
 __global__ void __launch_bounds__(kBlock)
 k_mx_update(int32_t n, int64_t S, const float *__restrict__ D, float *__restrict__ d,
             float *__restrict__ r, const float *__restrict__ p, const float *__restrict__ q,
-            double *partials, DevScalars *ds) {
+            double *partials, const DevScalars *ds) {
     if (ds->done || ds->inner_done) return;
     const float af = (float)ds->alpha;
     const int lane = threadIdx.x & 63;
@@ -425,7 +464,12 @@ k_mx_update(int32_t n, int64_t S, const float *__restrict__ D, float *__restrict
             acc[1] += (double)ri * (double)zi;
         }
     });
-    grid_reduce<2>(acc, partials, ds, [&](const double *t) {
+    block_partials<2>(acc, partials);
+}
+
+struct EpiMxInner {
+    __device__ bool active(const DevScalars *ds) const { return !(ds->done || ds->inner_done); }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
         const int it = ds->inner_iters + 1;
         ds->inner_iters = it;
         if (sqrt(t[0]) <= ds->inner_tol * ds->r0 || it >= ds->inner_max) {
@@ -434,8 +478,8 @@ k_mx_update(int32_t n, int64_t S, const float *__restrict__ D, float *__restrict
             ds->beta = t[1] / ds->rho;
             ds->rho = t[1];
         }
-    });
-}
+    }
+};
 
 __global__ void __launch_bounds__(kBlock)
 k_mx_p(int32_t n, int64_t S, const float *__restrict__ D, const float *__restrict__ r,
@@ -480,9 +524,7 @@ int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool 
     fill_stats_common(stats);
     set_scalars_for_solve(h, o.rel_tol, o.max_refine, st);
     k_mx_set_inner<<<1, 1, 0, st>>>(h->dev, o.inner_rel_tol, o.inner_max_iter);
-    k_residual<false, true><<<G, kBlock, 0, st>>>(A, b, x, h->r, nullptr, 0, kResCycle, 1,
-                                                  h->partials, h->dev, h->hist);
-    HIP_CHECK(hipGetLastError());
+    launch_residual<false, true>(h, A, b, x, h->r, nullptr, 0, kResCycle, true, st);
     read_scalars(h, st);
     DevScalars &hs = *h->host;
     if (stats) stats->initial_residual = hs.res;
@@ -502,11 +544,14 @@ int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool 
     while (hs.done == kRunning) {
         k_mx_start<<<G, kBlock, 0, st>>>(n, S, h->r, A32.diag, h->r32, h->d32, h->p32,
                                          h->partials, h->dev);
+        launch_finalize<2>(h->partials, G, h->dev, EpiMxStart{}, st);
         for (;;) {
             for (int k = 0; k < every; ++k) {
                 k_mx_q<<<G, kBlock, 0, st>>>(A32, h->p32, h->q32, h->partials, h->dev);
+                launch_finalize<1>(h->partials, G, h->dev, EpiMxAlpha{}, st);
                 k_mx_update<<<G, kBlock, 0, st>>>(n, S, A32.diag, h->d32, h->r32, h->p32,
                                                   h->q32, h->partials, h->dev);
+                launch_finalize<2>(h->partials, G, h->dev, EpiMxInner{}, st);
                 k_mx_p<<<G, kBlock, 0, st>>>(n, S, A32.diag, h->r32, h->p32, h->dev);
             }
             HIP_CHECK(hipGetLastError());
@@ -515,9 +560,7 @@ int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool 
         }
         inner_total += hs.inner_iters;
         k_mx_refine<<<G, kBlock, 0, st>>>(n, S, h->d32, x, h->dev);
-        k_residual<false, true><<<G, kBlock, 0, st>>>(A, b, x, h->r, nullptr, 0, kResCycle, 1,
-                                                      h->partials, h->dev, h->hist);
-        HIP_CHECK(hipGetLastError());
+        launch_residual<false, true>(h, A, b, x, h->r, nullptr, 0, kResCycle, true, st);
         read_scalars(h, st);
     }
     int status = LDU_OK;

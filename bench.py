@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--n", type=int, default=200)
     ap.add_argument("--full", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sweeps", type=int, default=1,
+                    help="Jacobi sweeps before and after the coarse correction")
     ap.add_argument("--amul-only", action="store_true",
                     help="only the Amul and copy timings (for counter runs)")
     args = ap.parse_args()
@@ -144,7 +146,7 @@ def main():
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
     t0 = time.perf_counter()
-    m.gamg_setup()
+    m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     nlev = m.n_levels()
@@ -235,8 +237,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"c3: {args.n}^3 graded hex, {case.n_cells} cells, "
                                f"{case.n_faces} faces, Dirichlet top, N(0,1) rhs",
-                   "solver": "CG + GAMG V-cycle (pairwise agglomeration, 2+2 Jacobi "
-                             "sweeps w=0.75, diagonal-CG coarsest)",
+                   "solver": f"CG + GAMG V-cycle (pairwise agglomeration, {args.sweeps}+"
+                             f"{args.sweeps} Jacobi sweeps w=0.75, diagonal-CG coarsest)",
                    "rel_tol": 1e-8, "x0": "zero"},
         "roofline": {"bound": "hbm", "kernel": "ldu_amul (k_amul<double>)",
                      "achieved": amul_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",

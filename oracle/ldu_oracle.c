@@ -661,10 +661,44 @@ static void set_singular(olevel *C) {
     free(one); free(y);
 }
 
+/* free the arrays of a level */
+static void free_level(olevel *L) {
+    free(L->own); free(L->nb); free(L->diag); free(L->up); free(L->lo);
+    free(L->diag32); free(L->up32); free(L->lo32);
+    free(L->agg); free(L->partner); free(L->join);
+    memset(L, 0, sizeof(*L));
+}
+
+/* aggregation of level L by `passes` rounds of pairwise agglomeration: pass
+ * k matches the cells of the Galerkin matrix of pass k-1 (a temporary used
+ * only for its coupling strengths), and the aggregates compose.  One pass is
+ * plain pairwise agglomeration.  Returns the number of aggregates and leaves
+ * the composed map in L->agg (partner/join describe the first pass). */
+static int32_t agglomerate_passes(olevel *L, int match_rounds, int passes) {
+    int32_t nc = agglomerate(L, match_rounds);
+    if (passes <= 1 || nc <= 1) return nc;
+    olevel T;
+    memset(&T, 0, sizeof T);
+    galerkin(L, nc, &T);
+    int32_t nc2 = agglomerate_passes(&T, match_rounds, passes - 1);
+    for (int32_t i = 0; i < L->n; ++i) L->agg[i] = T.agg[L->agg[i]];
+    free_level(&T);
+    return nc2;
+}
+
 orc_gamg *orc_gamg_build(int32_t n, int64_t nf, const int32_t *own,
                          const int32_t *nb, const double *diag,
                          const double *upper, const double *lower,
                          int n_coarsest, int max_levels, int match_rounds) {
+    return orc_gamg_build2(n, nf, own, nb, diag, upper, lower, n_coarsest,
+                           max_levels, match_rounds, 1);
+}
+
+orc_gamg *orc_gamg_build2(int32_t n, int64_t nf, const int32_t *own,
+                          const int32_t *nb, const double *diag,
+                          const double *upper, const double *lower,
+                          int n_coarsest, int max_levels, int match_rounds,
+                          int passes) {
     orc_gamg *h = xcalloc(1, sizeof(orc_gamg));
     if (max_levels > ORC_MAX_LEVELS) max_levels = ORC_MAX_LEVELS;
     if (max_levels < 1) max_levels = 1;
@@ -685,7 +719,7 @@ orc_gamg *orc_gamg_build(int32_t n, int64_t nf, const int32_t *own,
     while (h->nlev < max_levels) {
         olevel *L = &h->lev[h->nlev - 1];
         if (L->n <= n_coarsest) break;
-        int32_t nc = agglomerate(L, match_rounds);
+        int32_t nc = agglomerate_passes(L, match_rounds, passes);
         if (100 * (int64_t)nc > 95 * (int64_t)L->n) {
             free(L->agg); free(L->partner); free(L->join);
             L->agg = L->partner = L->join = NULL;
@@ -723,12 +757,7 @@ void orc_gamg_set_values(orc_gamg *h, const double *diag, const double *upper,
 
 void orc_gamg_free(orc_gamg *h) {
     if (!h) return;
-    for (int l = 0; l < h->nlev; ++l) {
-        olevel *L = &h->lev[l];
-        free(L->own); free(L->nb); free(L->diag); free(L->up); free(L->lo);
-        free(L->diag32); free(L->up32); free(L->lo32);
-        free(L->agg); free(L->partner); free(L->join);
-    }
+    for (int l = 0; l < h->nlev; ++l) free_level(&h->lev[l]);
     free(h);
 }
 

@@ -69,6 +69,13 @@ orc_gamg *orc_gamg_build(int32_t n, int64_t nf, const int32_t *own,
                          const int32_t *nb, const double *diag,
                          const double *upper, const double *lower,
                          int n_coarsest, int max_levels, int match_rounds);
+/* passes > 1: aggressive agglomeration (pairwise matching repeated on the
+ * Galerkin matrix of the previous pass, aggregates composed per level) */
+orc_gamg *orc_gamg_build2(int32_t n, int64_t nf, const int32_t *own,
+                          const int32_t *nb, const double *diag,
+                          const double *upper, const double *lower,
+                          int n_coarsest, int max_levels, int match_rounds,
+                          int passes);
 void orc_gamg_free(orc_gamg *h);
 /* new level-0 coefficients; aggregation kept, coarse matrices recomputed */
 void orc_gamg_set_values(orc_gamg *h, const double *diag, const double *upper,

@@ -74,6 +74,9 @@ def lib():
     L.orc_gamg_build.restype = vp
     L.orc_gamg_build.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p,
                                  C.c_int, C.c_int, C.c_int]
+    L.orc_gamg_build2.restype = vp
+    L.orc_gamg_build2.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p,
+                                  C.c_int, C.c_int, C.c_int, C.c_int]
     L.orc_gamg_free.argtypes = [vp]
     L.orc_gamg_set_values.argtypes = [vp, _f64p, _f64p, _f64p]
     L.orc_gamg_nlevels.argtypes = [vp]
@@ -203,10 +206,12 @@ class Level:
 class Gamg:
     """Oracle GAMG hierarchy (built once; values and structure fixed)."""
 
-    def __init__(self, A: Ldu, n_coarsest=50, max_levels=50, match_rounds=16):
+    def __init__(self, A: Ldu, n_coarsest=50, max_levels=50, match_rounds=16,
+                 passes=1):
         self.A = A
-        self._h = lib().orc_gamg_build(*A.args(), int(n_coarsest),
-                                       int(max_levels), int(match_rounds))
+        self._h = lib().orc_gamg_build2(*A.args(), int(n_coarsest),
+                                        int(max_levels), int(match_rounds),
+                                        int(passes))
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None

@@ -30,7 +30,7 @@ __device__ __forceinline__ void for_each_slice(int64_t S, F &&f) {
     const int64_t R = (S + nx - 1) / nx;
     const int64_t lo = x * R;
     const int64_t hi = (lo + R < S) ? lo + R : S;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     for (int64_t g = j; lo + g * kWavesPerBlock < hi; g += Gx) {
         const int64_t s = lo + g * kWavesPerBlock + w;
         if (s < hi) f(s);
@@ -109,6 +109,17 @@ inline void launch_finalize(double *partials, int nblocks, DevScalars *ds, const
     k_finalize<K, M, Epi><<<1, kBlock, 0, st>>>(partials, nblocks, ds, epi);
 }
 
+// row stored at slice position p, and the slice position of row i
+template <bool CMP, typename T>
+__device__ __forceinline__ int32_t sv_row(const SellView<T> &A, int64_t p) {
+    if constexpr (CMP) return A.perm[p];
+    else return (int32_t)p;
+}
+template <typename T>
+__device__ __forceinline__ int64_t sv_pos(const SellView<T> &A, int32_t i) {
+    return A.iperm ? (int64_t)A.iperm[i] : (int64_t)i;
+}
+
 // x accessors for the product kernels
 template <typename T>
 struct Direct {
@@ -122,23 +133,33 @@ struct ViaAgg {  // prolonged vector c_j = ec[agg[j]]
     __device__ __forceinline__ T operator()(int32_t j) const { return ec[agg[j]]; }
 };
 
-// (A x)_i for row i = 64 s + lane of slice s
-template <typename T, class XA>
+// (A x)_i for the row i stored at position 64 s + lane of slice s; CMP
+// selects the compressed-slice layout at compile time (each layout gets its
+// own kernels, so the plain one keeps its register budget and occupancy)
+template <bool CMP, typename T, class XA>
 __device__ __forceinline__ T sell_row(const SellView<T> &A, int64_t s, int lane,
                                       int32_t i, const XA &xa) {
     const int64_t b0 = A.sptr[s];
-    const int w = (int)((A.sptr[s + 1] - b0) >> 6);
+    T acc = A.diag[i] * xa(i);
     const int32_t *cp = A.col + b0 + lane;
     const T *vp = A.val + b0 + lane;
-    T acc = A.diag[i] * xa(i);
+    int w;
+    const int32_t *ot = nullptr;
+    if constexpr (CMP) {
+        w = A.pdeg[s * kWave + lane];
+        ot = A.otab + A.tptr[s];
+    } else {
+        w = (int)((A.sptr[s + 1] - b0) >> 6);
+    }
     for (int k = 0; k < w; k += 8) {
         int32_t c[8];
         T v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (k + u < w) {
-                c[u] = __builtin_nontemporal_load(cp + (int64_t)(k + u) * kWave);
-                v[u] = __builtin_nontemporal_load(vp + (int64_t)(k + u) * kWave);
+                const int64_t o = CMP ? (int64_t)ot[k + u] : (int64_t)(k + u) * kWave;
+                c[u] = __builtin_nontemporal_load(cp + o);
+                v[u] = __builtin_nontemporal_load(vp + o);
             }
         }
         T xv[8];
@@ -150,6 +171,28 @@ __device__ __forceinline__ T sell_row(const SellView<T> &A, int64_t s, int lane,
             if (k + u < w) acc = acc + v[u] * xv[u];
     }
     return acc;
+}
+
+// either layout, decided at run time (small levels and setup kernels)
+template <typename T, class XA>
+__device__ __forceinline__ T sell_row_any(const SellView<T> &A, int64_t s, int lane, int32_t i,
+                                          const XA &xa) {
+    return A.pdeg ? sell_row<true>(A, s, lane, i, xa) : sell_row<false>(A, s, lane, i, xa);
+}
+
+// entry count of the row at slice position p, and the storage index of its
+// k-th entry (either layout)
+template <class M>
+__device__ __forceinline__ int row_len(const M &A, int64_t p) {
+    if (A.pdeg) return A.pdeg[p];
+    const int64_t s = p >> 6;
+    return (int)((A.sptr[s + 1] - A.sptr[s]) >> 6);  // includes padding (col == row)
+}
+template <class M>
+__device__ __forceinline__ int64_t entry_at(const M &A, int64_t p, int k) {
+    const int64_t s = p >> 6, lane = p & 63;
+    if (A.pdeg) return A.sptr[s] + A.otab[A.tptr[s] + k] + lane;
+    return A.sptr[s] + (int64_t)k * kWave + lane;
 }
 
 }  // namespace ldu

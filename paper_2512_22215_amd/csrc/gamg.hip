@@ -68,14 +68,13 @@ static unsigned grid_n(int64_t n) {
 // best neighbour of row i among those whose matched state equals want_matched
 __device__ int32_t best_neighbour(const Sell &A, int32_t i, const int32_t *partner,
                                   bool want_matched) {
-    const int64_t s = i >> 6, lane = i & 63;
-    const int64_t b0 = A.sptr[s];
-    const int w = (int)((A.sptr[s + 1] - b0) >> 6);
+    const int64_t ps = A.iperm ? (int64_t)A.iperm[i] : (int64_t)i;
+    const int w = row_len(A, ps);
     int32_t best = -1;
     double bw = 0.0;
     uint64_t bh = 0;
     for (int k = 0; k < w; ++k) {
-        const int64_t pos = b0 + (int64_t)k * kWave + lane;
+        const int64_t pos = entry_at(A, ps, k);
         const int32_t c = A.col[pos];
         if (c == i) continue;  // padding
         if ((partner[c] >= 0) != want_matched) continue;
@@ -169,11 +168,10 @@ __device__ int coarse_row(const Sell &A, const int32_t *agg, const int32_t *star
     int m = 0;
     for (int32_t k = start[a]; k < start[a + 1]; ++k) {
         const int32_t i = cells[k];
-        const int64_t s = i >> 6, lane = i & 63;
-        const int64_t b0 = A.sptr[s];
-        const int w = (int)((A.sptr[s + 1] - b0) >> 6);
+        const int64_t ps = A.iperm ? (int64_t)A.iperm[i] : (int64_t)i;
+        const int w = row_len(A, ps);
         for (int e = 0; e < w; ++e) {
-            const int32_t c = A.col[b0 + (int64_t)e * kWave + lane];
+            const int32_t c = A.col[entry_at(A, ps, e)];
             if (c == i) continue;
             const int32_t b = agg[c];
             if (b <= a) continue;
@@ -253,10 +251,11 @@ __global__ void k_coarse_diag(int32_t nc, const int32_t *agg, const int32_t *sta
 // singular level: |(A 1)_i| <= 1e-12 |diag_i| for every row
 __global__ void k_singular(Sell A, int *flag) {
     GRID_STRIDE(i, A.n) {
-        const int64_t s = i >> 6, lane = i & 63;
+        const int64_t ps = A.iperm ? (int64_t)A.iperm[i] : (int64_t)i;
+        const int64_t s = ps >> 6, lane = ps & 63;
         const SellView<double> v = A.view(false);
         struct One { __device__ double operator()(int32_t) const { return 1.0; } };
-        const double y = sell_row(v, s, (int)lane, (int32_t)i, One{});
+        const double y = sell_row_any(v, s, (int)lane, (int32_t)i, One{});
         if (!(fabs(y) <= 1e-12 * fabs(A.diag[i]))) atomicAnd(flag, 0);
     }
 }
@@ -389,6 +388,7 @@ void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
     }
     for (auto &L : h->levels) alloc_work(L, ar);
     h->coarse_work = ar.get<double>(4 * (size_t)h->levels.back().n);
+
     if (h->L0.A.val32) ensure_f32_levels(h, st);
     detect_singular(h, h->levels.back(), st);
     h->gamg_opts = o;
@@ -433,31 +433,35 @@ k_vc_zero(int32_t n, int64_t S, T *__restrict__ e, const DevScalars *ds) {
 }
 
 // e_out = e + omega (r - A e) / D
-template <typename T>
+template <bool CMP, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
             T *__restrict__ eo, T omega, const DevScalars *ds) {
     if (ds->done) return;
     const int lane = threadIdx.x & 63;
     for_each_slice(A.nslices, [&](int64_t s) {
-        const int64_t i = s * kWave + lane;
-        if (i < A.n) {
-            const T y = sell_row(A, s, lane, (int32_t)i, Direct<T>{e});
+        const int64_t p = s * kWave + lane;
+        if (p < A.n) {
+            const int32_t i = sv_row<CMP>(A, p);
+            const T y = sell_row<CMP>(A, s, lane, i, Direct<T>{e});
             eo[i] = e[i] + omega * (r[i] - y) / A.diag[i];
         }
     });
 }
 
 // t = r - A e
-template <typename T>
+template <bool CMP, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_resid(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
            T *__restrict__ t, const DevScalars *ds) {
     if (ds->done) return;
     const int lane = threadIdx.x & 63;
     for_each_slice(A.nslices, [&](int64_t s) {
-        const int64_t i = s * kWave + lane;
-        if (i < A.n) t[i] = r[i] - sell_row(A, s, lane, (int32_t)i, Direct<T>{e});
+        const int64_t p = s * kWave + lane;
+        if (p < A.n) {
+            const int32_t i = sv_row<CMP>(A, p);
+            t[i] = r[i] - sell_row<CMP>(A, s, lane, i, Direct<T>{e});
+        }
     });
 }
 
@@ -475,7 +479,7 @@ k_vc_restrict(int32_t nc, const int32_t *__restrict__ start, const int32_t *__re
 }
 
 // c = P e_c; s = (c . t) / (c . A c), or 1 when c.Ac is ~0
-template <typename T>
+template <bool CMP, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_scale(SellView<T> A, const T *__restrict__ ec, const int32_t *__restrict__ agg,
            const T *__restrict__ t, double *partials, const DevScalars *ds) {
@@ -483,9 +487,10 @@ k_vc_scale(SellView<T> A, const T *__restrict__ ec, const int32_t *__restrict__ 
     const int lane = threadIdx.x & 63;
     double acc[2] = {0.0, 0.0};
     for_each_slice(A.nslices, [&](int64_t s) {
-        const int64_t i = s * kWave + lane;
-        if (i < A.n) {
-            const T ac = sell_row(A, s, lane, (int32_t)i, ViaAgg<T>{ec, agg});
+        const int64_t p = s * kWave + lane;
+        if (p < A.n) {
+            const int32_t i = sv_row<CMP>(A, p);
+            const T ac = sell_row<CMP>(A, s, lane, i, ViaAgg<T>{ec, agg});
             const T ci = ec[agg[i]];
             acc[0] += (double)ci * (double)t[i];
             acc[1] += (double)ci * (double)ac;
@@ -518,82 +523,181 @@ k_vc_correct(int32_t n, int64_t S, const T *__restrict__ ec, const int32_t *__re
 // coarsest level: diagonal PCG in FP64 by one workgroup, from e = 0 to
 // ||r|| <= tol ||rhs|| or max_it iterations; a singular level first
 // projects its rhs to zero mean.  w: 3 n doubles of scratch (r, p, q).
-template <int K>
+template <int K, int NW>
 __device__ __forceinline__ void bcast_sum(double (&v)[K]) {
-    __shared__ double out[K];
-    block_reduce<K>(v);
-    if (threadIdx.x == 0) {
+    if constexpr (NW == 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) out[k] = v[k];
+        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);  // every lane gets the sum
+    } else {
+        __shared__ double out[K];
+        block_reduce<K>(v);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) out[k] = v[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = out[k];
+        __syncthreads();
     }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = out[k];
+}
+
+// LDS holds the coarsest CG vectors when 4 n doubles fit (dynamic shared memory)
+constexpr int kLdsCoarse = 1536;
+
+// a barrier also in the one-wavefront case (there it costs next to nothing
+// and orders the LDS stores of one lane before other lanes' loads)
+template <int NW>
+__device__ __forceinline__ void csync() {
     __syncthreads();
 }
 
-template <typename TI>
-__global__ void __launch_bounds__(kBlock)
-k_coarsest(SellView<double> A, const TI *__restrict__ rhs, TI *__restrict__ eo,
-           double *__restrict__ w, int singular, double tol, int max_it, const DevScalars *ds) {
-    if (ds->done) return;
+template <typename TI, int NW>
+__device__ void coarsest_body(const SellView<double> &A, const TI *__restrict__ rhs,
+                              TI *__restrict__ eo, double *__restrict__ w, int singular,
+                              double tol, int max_it) {
+    constexpr int NT = NW * kWave;
     const int32_t n = A.n;
     double *r = w, *p = w + n, *q = w + 2 * (int64_t)n, *x = w + 3 * (int64_t)n;
-    for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+    for (int32_t i = threadIdx.x; i < n; i += NT) {
         r[i] = (double)rhs[i];
         x[i] = 0.0;
     }
-    __syncthreads();
+    csync<NW>();
     if (singular) {
         double m[1] = {0.0};
-        for (int32_t i = threadIdx.x; i < n; i += kBlock) m[0] += r[i];
-        bcast_sum<1>(m);
+        for (int32_t i = threadIdx.x; i < n; i += NT) m[0] += r[i];
+        bcast_sum<1, NW>(m);
         const double mean = m[0] / (double)n;
-        for (int32_t i = threadIdx.x; i < n; i += kBlock) r[i] = r[i] - mean;
-        __syncthreads();
+        for (int32_t i = threadIdx.x; i < n; i += NT) r[i] = r[i] - mean;
+        csync<NW>();
     }
     double b2[1] = {0.0};
-    for (int32_t i = threadIdx.x; i < n; i += kBlock) b2[0] += r[i] * r[i];
-    bcast_sum<1>(b2);
+    for (int32_t i = threadIdx.x; i < n; i += NT) b2[0] += r[i] * r[i];
+    bcast_sum<1, NW>(b2);
     const double bn = sqrt(b2[0]);
     if (bn > 0.0) {
         double rz[1] = {0.0};
-        for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+        for (int32_t i = threadIdx.x; i < n; i += NT) {
             const double zi = r[i] / A.diag[i];
             p[i] = zi;
             rz[0] += r[i] * zi;
         }
-        bcast_sum<1>(rz);
+        bcast_sum<1, NW>(rz);
         double rho = rz[0];
         for (int it = 0; it < max_it; ++it) {
             double pq[1] = {0.0};
-            for (int32_t i = threadIdx.x; i < n; i += kBlock) {
-                const double qi = sell_row(A, i >> 6, i & 63, i, Direct<double>{p});
+            for (int32_t i = threadIdx.x; i < n; i += NT) {
+                const int64_t ps = sv_pos(A, i);
+                const double qi = sell_row_any(A, ps >> 6, (int)(ps & 63), i, Direct<double>{p});
                 q[i] = qi;
                 pq[0] += p[i] * qi;
             }
-            bcast_sum<1>(pq);
+            bcast_sum<1, NW>(pq);
             if (!isfinite(pq[0]) || fabs(pq[0]) <= 1e-300) break;
             const double alpha = rho / pq[0];
             double acc[2] = {0.0, 0.0};
-            for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+            for (int32_t i = threadIdx.x; i < n; i += NT) {
                 x[i] = x[i] + alpha * p[i];
                 const double ri = r[i] - alpha * q[i];
                 r[i] = ri;
                 acc[0] += ri * ri;
                 acc[1] += ri * (ri / A.diag[i]);
             }
-            bcast_sum<2>(acc);
+            bcast_sum<2, NW>(acc);
             if (sqrt(acc[0]) / bn <= tol) break;
             const double beta = acc[1] / rho;
             rho = acc[1];
-            for (int32_t i = threadIdx.x; i < n; i += kBlock)
+            for (int32_t i = threadIdx.x; i < n; i += NT)
                 p[i] = r[i] / A.diag[i] + beta * p[i];
-            __syncthreads();
+            csync<NW>();
         }
     }
-    __syncthreads();
-    for (int32_t i = threadIdx.x; i < n; i += kBlock) eo[i] = (TI)x[i];
+    csync<NW>();
+    for (int32_t i = threadIdx.x; i < n; i += NT) eo[i] = (TI)x[i];
+}
+
+
+// coarsest level of at most 64 cells with rows of at most kWaveRow entries:
+// one wavefront, one row per lane, the row's entries held in LDS
+// (entry-major, so lanes read distinct banks) and the search direction in
+// LDS.  Row i sums diag_i p_i first and then its entries in column order, as
+// the sparse kernels do.
+constexpr int kWaveRow = 48;
+
+__global__ void __launch_bounds__(kWave)
+k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
+                const float *__restrict__ rhs_f, double *__restrict__ eo_d,
+                float *__restrict__ eo_f, int singular, double tol, int max_it,
+                const DevScalars *ds) {
+    __shared__ int32_t cL[kWaveRow * kWave];
+    __shared__ double vL[kWaveRow * kWave];
+    __shared__ double p[kWave];
+    if (ds->done) return;
+    const int32_t n = A.n;
+    const int i = threadIdx.x;
+    double di = 1.0, ri = 0.0;
+    int m = 0;
+    if (i < n) {
+        const int64_t ps = sv_pos(A, i);
+        const int w = row_len(A, ps);
+        for (int k = 0; k < w; ++k) {
+            const int64_t e = entry_at(A, ps, k);
+            const int32_t c = A.col[e];
+            if (c == i) continue;  // padding entries point at the row
+            cL[m * kWave + i] = c;
+            vL[m * kWave + i] = A.val[e];
+            ++m;
+        }
+        di = A.diag[i];
+        ri = rhs_d ? rhs_d[i] : (double)rhs_f[i];
+    }
+    if (singular) {
+        const double mean = wave_sum(ri) / (double)n;
+        if (i < n) ri = ri - mean;
+    }
+    double xi = 0.0;
+    const double bn = sqrt(wave_sum(ri * ri));
+    if (bn > 0.0) {
+        double pi = (i < n) ? ri / di : 0.0;
+        double rho = wave_sum(ri * pi);
+        for (int it = 0; it < max_it; ++it) {
+            p[i] = pi;
+            __syncthreads();
+            double qi = 0.0;
+            if (i < n) {
+                qi = di * pi;
+                for (int k = 0; k < m; ++k) qi = qi + vL[k * kWave + i] * p[cL[k * kWave + i]];
+            }
+            __syncthreads();
+            const double pq = wave_sum(pi * qi);
+            if (!isfinite(pq) || fabs(pq) <= 1e-300) break;
+            const double alpha = rho / pq;
+            xi = xi + alpha * pi;
+            ri = ri - alpha * qi;
+            const double zi = (i < n) ? ri / di : 0.0;
+            const double rr = wave_sum(ri * ri);
+            const double rz = wave_sum(ri * zi);
+            if (sqrt(rr) / bn <= tol) break;
+            const double beta = rz / rho;
+            rho = rz;
+            pi = zi + beta * pi;
+        }
+    }
+    if (i < n) {
+        if (eo_d) eo_d[i] = xi;
+        else eo_f[i] = (float)xi;
+    }
+}
+
+// coarsest-level launch for larger levels: one 256-thread block
+template <typename TI, int NW>
+__global__ void __launch_bounds__(kBlock)
+k_coarsest(SellView<double> A, const TI *__restrict__ rhs, TI *__restrict__ eo,
+           double *__restrict__ w, int singular, double tol, int max_it, const DevScalars *ds) {
+    extern __shared__ double lds_w[];
+    if (ds->done) return;
+    coarsest_body<TI, NW>(A, rhs, eo, A.n <= kLdsCoarse ? lds_w : w, singular, tol, max_it);
 }
 
 // x += e (GAMG correction of the outer FP64 loop)
@@ -634,6 +738,13 @@ k_refine_add(int32_t n, int64_t S, const float *__restrict__ d, double *__restri
     });
 }
 
+template <typename T>
+static void launch_jacobi(const SellView<T> &A, const T *r, const T *e, T *eo, T omega,
+                          const DevScalars *ds, int G, hipStream_t st) {
+    if (A.pdeg) k_vc_jacobi<true, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, ds);
+    else k_vc_jacobi<false, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, ds);
+}
+
 // ---------------------------------------------------------------- V-cycle driver
 struct VCtx {
     ldu_t *h;
@@ -666,12 +777,20 @@ static T *vcycle(const VCtx &c, size_t l, const T *r) {
     ldu_t *h = c.h;
     Level &L = h->levels[l];
     hipStream_t st = c.st;
-    const bool last = (l + 1 == h->levels.size());
     T *e = lvec<T>(L, 1), *e2 = lvec<T>(L, 2), *t = lvec<T>(L, 3);
-    if (last) {
+    if (l + 1 == h->levels.size()) {
         const int maxit = std::max(2 * L.n, 100);
-        k_coarsest<T><<<1, kBlock, 0, st>>>(L.A.view(c.tr), r, e, c.cw, L.singular,
-                                            kCoarsestTol, maxit, h->dev);
+        const size_t lds = L.n <= kLdsCoarse ? sizeof(double) * 4 * L.n : 0;
+        if (L.n <= kWave && L.max_row <= kWaveRow) {
+            const bool f64 = sizeof(T) == sizeof(double);
+            k_coarsest_wave<<<1, kWave, 0, st>>>(
+                L.A.view(c.tr), f64 ? (const double *)r : nullptr,
+                f64 ? nullptr : (const float *)r, f64 ? (double *)e : nullptr,
+                f64 ? nullptr : (float *)e, L.singular, kCoarsestTol, maxit, h->dev);
+        } else
+            k_coarsest<T, kWavesPerBlock><<<1, kBlock, lds, st>>>(L.A.view(c.tr), r, e, c.cw,
+                                                                 L.singular, kCoarsestTol,
+                                                                 maxit, h->dev);
         HIP_CHECK(hipGetLastError());
         return e;
     }
@@ -682,21 +801,23 @@ static T *vcycle(const VCtx &c, size_t l, const T *r) {
     if (c.o->n_pre > 0) k_vc_first<T><<<G, kBlock, 0, st>>>(L.n, S, r, A.diag, e, omega, h->dev);
     else k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
     for (int k = 1; k < c.o->n_pre; ++k) {
-        k_vc_jacobi<T><<<G, kBlock, 0, st>>>(A, r, e, e2, omega, h->dev);
+        launch_jacobi<T>(A, r, e, e2, omega, h->dev, G, st);
         std::swap(e, e2);
     }
-    k_vc_resid<T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
+    if (A.pdeg) k_vc_resid<true, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
+    else k_vc_resid<false, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
     Level &C = h->levels[l + 1];
     T *rc = lvec<T>(C, 0);
     k_vc_restrict<T><<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, t, rc, h->dev);
     const T *ec = vcycle<T>(c, l + 1, rc);
     if (c.o->scale_correction) {
-        k_vc_scale<T><<<G, kBlock, 0, st>>>(A, ec, L.agg, t, h->partials, h->dev);
+        if (A.pdeg) k_vc_scale<true, T><<<G, kBlock, 0, st>>>(A, ec, L.agg, t, h->partials, h->dev);
+        else k_vc_scale<false, T><<<G, kBlock, 0, st>>>(A, ec, L.agg, t, h->partials, h->dev);
         launch_finalize<2>(h->partials, G, h->dev, EpiScale{}, st);
     }
     k_vc_correct<T><<<G, kBlock, 0, st>>>(L.n, S, ec, L.agg, e, c.o->scale_correction, h->dev);
     for (int k = 0; k < c.o->n_post; ++k) {
-        k_vc_jacobi<T><<<G, kBlock, 0, st>>>(A, r, e, e2, omega, h->dev);
+        launch_jacobi<T>(A, r, e, e2, omega, h->dev, G, st);
         std::swap(e, e2);
     }
     HIP_CHECK(hipGetLastError());

@@ -11,6 +11,14 @@
 //    below the row) first, then the "upper" ones.  Padding entries point at
 //    their own row with value 0.  val holds A, valT holds A^T at the same
 //    positions, so the transposed product runs the same kernel.
+//  - levels whose row lengths vary (the Galerkin coarse levels: 3 to ~27
+//    entries, which pads max-width slices by 40-50%) use compressed slices:
+//    inside each slice of 64 rows the rows are ordered by length (longest
+//    first; perm maps a slice position to its row, iperm back), and entry k
+//    of lane l is stored at sptr[s] + otab[tptr[s] + k] + l, where
+//    otab[tptr[s] + k] counts the entries of the slice's first k columns.
+//    Nothing is padded, and a row's loads and stores stay inside the slice's
+//    own cache lines.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,6 +62,11 @@ struct SellView {
     const int32_t *col;
     const T *val;
     const T *diag;
+    const int32_t *perm;   // row stored at slice position p (NULL: identity)
+    const int32_t *iperm;  // slice position of row i (NULL: identity)
+    const int32_t *pdeg;   // compressed slices: entries of the row at position p
+    const int32_t *tptr;   // compressed slices: start of slice s in otab
+    const int32_t *otab;   // compressed slices: offset of entry k within slice s
 };
 
 // scalars shared between the kernels of one solve; device resident
@@ -93,19 +106,21 @@ private:
 struct Sell {
     int32_t n = 0;
     int64_t nslices = 0, nnz = 0;
-    int maxw = 0;
     int64_t *sptr = nullptr;
     int32_t *col = nullptr;
     double *val = nullptr, *valT = nullptr;
     float *val32 = nullptr, *valT32 = nullptr;
     double *diag = nullptr;
     float *diag32 = nullptr;
+    // compressed slices (levels with uneven rows): lanes sorted by row length
+    int32_t *perm = nullptr, *iperm = nullptr, *pdeg = nullptr, *tptr = nullptr, *otab = nullptr;
 
     __host__ __device__ SellView<double> view(bool transpose) const {
-        return {n, nslices, sptr, col, transpose ? valT : val, diag};
+        return {n, nslices, sptr, col, transpose ? valT : val, diag, perm, iperm, pdeg, tptr, otab};
     }
     __host__ __device__ SellView<float> view32(bool transpose) const {
-        return {n, nslices, sptr, col, transpose ? valT32 : val32, diag32};
+        return {n, nslices, sptr, col, transpose ? valT32 : val32, diag32, perm, iperm, pdeg,
+                tptr, otab};
     }
 };
 
@@ -121,6 +136,7 @@ struct Level {
     int32_t nc = 0;
     int32_t *agg = nullptr, *aggStart = nullptr, *aggCells = nullptr;
     int singular = 0;                     // coarsest level: A 1 = 0
+    int max_row = 0;                      // longest row (off-diagonal entries)
     // V-cycle work vectors
     double *r = nullptr, *e = nullptr, *e2 = nullptr, *t = nullptr;
     float *r32 = nullptr, *e32 = nullptr, *e232 = nullptr, *t32 = nullptr;

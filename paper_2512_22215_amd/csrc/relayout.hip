@@ -10,6 +10,8 @@
 // scattered in place without redoing the structure.
 #include "device.hpp"
 
+#include <algorithm>
+
 namespace ldu {
 
 // ---------------------------------------------------------------- scans
@@ -156,16 +158,22 @@ __global__ void k_count_lower(int64_t nf, const int32_t *nb, int32_t *cntL) {
         atomicAdd(&cntL[nb[f]], 1);
 }
 
-// width of slice s (max row length) times 64 = entries in the slice
-__global__ void k_slice_entries(int32_t n, int64_t S, const int64_t *ownStart,
-                                const int32_t *cntL, int64_t *entries) {
+__global__ void k_degree(int32_t n, const int64_t *ownStart, const int32_t *cntL, int32_t *deg) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        deg[i] = cntL[i] + (int32_t)(ownStart[i + 1] - ownStart[i]);
+}
+
+// entries of slice s = 64 x (longest row stored in the slice)
+__global__ void k_slice_entries(int32_t n, int64_t S, const int32_t *deg, const int32_t *perm,
+                                int64_t *entries) {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S;
          s += (int64_t)gridDim.x * blockDim.x) {
         int64_t w = 0;
         for (int l = 0; l < kWave; ++l) {
-            const int64_t i = s * kWave + l;
-            if (i < n) {
-                int64_t d = cntL[i] + (ownStart[i + 1] - ownStart[i]);
+            const int64_t p = s * kWave + l;
+            if (p < n) {
+                const int64_t d = deg[perm ? perm[p] : p];
                 w = d > w ? d : w;
             }
         }
@@ -173,17 +181,93 @@ __global__ void k_slice_entries(int32_t n, int64_t S, const int64_t *ownStart,
     }
 }
 
-__device__ __forceinline__ int64_t sell_pos(const int64_t *sptr, int64_t i, int64_t k) {
-    return sptr[i >> 6] + k * kWave + (i & 63);
+// compressed slices: inside each slice of 64 rows, order the rows by length
+// (longest first, ties by row index); positions past n hold no row (-1)
+__global__ void k_slice_sort(int32_t n, int64_t S, const int32_t *deg, int32_t *perm,
+                             int32_t *iperm, int32_t *pdeg) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < S * kWave;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s0 = (q >> 6) << 6;
+        const int l = (int)(q & 63);
+        const int32_t dl = q < n ? deg[q] : -1;
+        int rank = 0;
+        for (int j = 0; j < kWave; ++j) {
+            const int32_t dj = (s0 + j) < n ? deg[s0 + j] : -1;
+            rank += (dj > dl) || (dj == dl && j < l);
+        }
+        perm[s0 + rank] = q < n ? (int32_t)q : -1;
+        pdeg[s0 + rank] = dl > 0 ? dl : 0;
+        if (q < n) iperm[q] = (int32_t)(s0 + rank);
+    }
 }
 
+// entries of a compressed slice (sum of its row lengths) and the length of
+// its offset table (longest row + 1)
+__global__ void k_slice_sizes(int64_t S, const int32_t *pdeg, int64_t *entries, int32_t *tlen) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        int64_t e = 0;
+        for (int l = 0; l < kWave; ++l) e += pdeg[s * kWave + l];
+        entries[s] = e;
+        tlen[s] = pdeg[s * kWave] + 1;
+    }
+}
+
+// otab[tptr[s] + k] = entries of slice s in its columns 0..k-1
+__global__ void k_slice_table(int64_t S, const int32_t *pdeg, const int32_t *tptr, int32_t *otab) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int w = pdeg[s * kWave];
+        int32_t off = 0;
+        for (int k = 0; k <= w; ++k) {
+            otab[tptr[s] + k] = off;
+            int cnt = 0;
+            for (int l = 0; l < kWave; ++l) cnt += pdeg[s * kWave + l] > k;
+            off += cnt;
+        }
+    }
+}
+
+// max of a[0..n) by one block
+__global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t *a, int64_t n, int32_t *out) {
+    __shared__ int32_t sm[kBlock];
+    int32_t m = 0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) m = a[i] > m ? a[i] : m;
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < (unsigned)off && sm[threadIdx.x + off] > sm[threadIdx.x])
+            sm[threadIdx.x] = sm[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sm[0];
+}
+
+__global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+// storage index of entry k of row i (plain or compressed slices)
+struct Slots {
+    const int64_t *sptr;
+    const int32_t *iperm, *tptr, *otab;
+    __device__ __forceinline__ int64_t operator()(int64_t i, int64_t k) const {
+        const int64_t p = iperm ? (int64_t)iperm[i] : i;
+        const int64_t s = p >> 6;
+        if (otab) return sptr[s] + otab[tptr[s] + k] + (p & 63);
+        return sptr[s] + k * kWave + (p & 63);
+    }
+};
+
 __global__ void k_fill_upper(int64_t nf, const int32_t *own, const int32_t *nb,
-                             const int64_t *ownStart, const int32_t *cntL,
-                             const int64_t *sptr, int32_t *col, int64_t *slotU) {
+                             const int64_t *ownStart, const int32_t *cntL, Slots slot,
+                             int32_t *col, int64_t *slotU) {
     for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nf;
          f += (int64_t)gridDim.x * blockDim.x) {
         const int32_t i = own[f];
-        const int64_t pos = sell_pos(sptr, i, cntL[i] + (f - ownStart[i]));
+        const int64_t pos = slot(i, cntL[i] + (f - ownStart[i]));
         col[pos] = nb[f];
         slotU[f] = pos;
     }
@@ -191,57 +275,58 @@ __global__ void k_fill_upper(int64_t nf, const int32_t *own, const int32_t *nb,
 
 // lower entries land in arbitrary order within their row; k_sort_lower
 // orders them by column, which makes the final layout deterministic
-__global__ void k_fill_lower(int64_t nf, const int32_t *own, const int32_t *nb,
-                             const int64_t *sptr, int32_t *cursor, int32_t *col,
-                             int64_t *faceAt) {
+__global__ void k_fill_lower(int64_t nf, const int32_t *own, const int32_t *nb, Slots slot,
+                             int32_t *cursor, int32_t *col, int64_t *faceAt) {
     for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nf;
          f += (int64_t)gridDim.x * blockDim.x) {
         const int32_t j = nb[f];
         const int k = atomicAdd(&cursor[j], 1);
-        const int64_t pos = sell_pos(sptr, j, k);
+        const int64_t pos = slot(j, k);
         col[pos] = own[f];
         faceAt[pos] = f;
     }
 }
 
-__global__ void k_sort_lower(int32_t n, const int64_t *sptr, const int32_t *cntL,
-                             int32_t *col, int64_t *faceAt, int64_t *slotL) {
+__global__ void k_sort_lower(int32_t n, Slots slot, const int32_t *cntL, int32_t *col,
+                             int64_t *faceAt, int64_t *slotL) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x) {
         const int m = cntL[j];
         for (int a = 1; a < m; ++a) {  // insertion sort by column
-            const int64_t pa = sell_pos(sptr, j, a);
+            const int64_t pa = slot(j, a);
             const int32_t c = col[pa];
             const int64_t fa = faceAt[pa];
             int b = a - 1;
-            while (b >= 0 && col[sell_pos(sptr, j, b)] > c) {
-                const int64_t pb = sell_pos(sptr, j, b), pn = sell_pos(sptr, j, b + 1);
+            while (b >= 0 && col[slot(j, b)] > c) {
+                const int64_t pb = slot(j, b), pn = slot(j, b + 1);
                 col[pn] = col[pb];
                 faceAt[pn] = faceAt[pb];
                 --b;
             }
-            const int64_t pn = sell_pos(sptr, j, b + 1);
+            const int64_t pn = slot(j, b + 1);
             col[pn] = c;
             faceAt[pn] = fa;
         }
         for (int a = 0; a < m; ++a) {
-            const int64_t pa = sell_pos(sptr, j, a);
+            const int64_t pa = slot(j, a);
             slotL[faceAt[pa]] = pa;
         }
     }
 }
 
-__global__ void k_fill_pad(int32_t n, int64_t S, const int64_t *sptr, const int64_t *ownStart,
-                           const int32_t *cntL, int32_t *col, double *val, double *valT) {
+// plain slices: padding entries point at their own row with value 0
+// (positions past n: row 0)
+__global__ void k_fill_pad(int32_t n, int64_t S, const int64_t *sptr, const int32_t *deg,
+                           int32_t *col, double *val, double *valT) {
     const int64_t rows = S * kWave;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t s = i >> 6;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < rows;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = p >> 6;
         const int64_t w = (sptr[s + 1] - sptr[s]) >> 6;
-        const int64_t d = (i < n) ? cntL[i] + (ownStart[i + 1] - ownStart[i]) : 0;
+        const int64_t d = (p < n) ? deg[p] : 0;
         for (int64_t k = d; k < w; ++k) {
-            const int64_t pos = sell_pos(sptr, i, k);
-            col[pos] = (i < n) ? (int32_t)i : 0;
+            const int64_t pos = sptr[s] + k * kWave + (p & 63);
+            col[pos] = (p < n) ? (int32_t)p : 0;
             val[pos] = 0.0;
             valT[pos] = 0.0;
         }
@@ -290,13 +375,43 @@ void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t 
     int32_t *cntL = tmp.get<int32_t>(n);
     HIP_CHECK(hipMemsetAsync(cntL, 0, sizeof(int32_t) * n, st));
     if (nf > 0) k_count_lower<<<grid_for(nf), kBlock, 0, st>>>(nf, L.nb, cntL);
+    int32_t *deg = tmp.get<int32_t>(n);
+    k_degree<<<grid_for(n), kBlock, 0, st>>>(n, L.ownStart, cntL, deg);
     int64_t *entries = tmp.get<int64_t>(S);
-    k_slice_entries<<<grid_for(S), kBlock, 0, st>>>(n, S, L.ownStart, cntL, entries);
     L.A.sptr = ar.get<int64_t>(S + 1);
+    k_slice_entries<<<grid_for(S), kBlock, 0, st>>>(n, S, deg, nullptr, entries);
     exclusive_scan_i64(entries, L.A.sptr, S, tmp, st);
     int64_t nnz = 0;
     HIP_CHECK(hipMemcpyAsync(&nnz, L.A.sptr + S, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
+    L.A.perm = L.A.iperm = L.A.pdeg = L.A.tptr = L.A.otab = nullptr;
+    if (nnz * 100 > 103 * std::max<int64_t>(2 * nf, kWave)) {
+        // rows of uneven length: compressed slices, lanes ordered by length
+        L.A.perm = ar.get<int32_t>(S * kWave);
+        L.A.iperm = ar.get<int32_t>(n);
+        L.A.pdeg = ar.get<int32_t>(S * kWave);
+        k_slice_sort<<<grid_for(S * kWave), kBlock, 0, st>>>(n, S, deg, L.A.perm, L.A.iperm,
+                                                             L.A.pdeg);
+        int32_t *tlen = tmp.get<int32_t>(S);
+        k_slice_sizes<<<grid_for(S), kBlock, 0, st>>>(S, L.A.pdeg, entries, tlen);
+        exclusive_scan_i64(entries, L.A.sptr, S, tmp, st);
+        L.A.tptr = ar.get<int32_t>(S + 1);
+        scan_counts_i32(tlen, L.A.tptr, S, tmp, st);
+        int32_t ntab = 0;
+        HIP_CHECK(hipMemcpyAsync(&ntab, L.A.tptr + S, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                 st));
+        HIP_CHECK(hipMemcpyAsync(&nnz, L.A.sptr + S, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                 st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        L.A.otab = ar.get<int32_t>(ntab);
+        k_slice_table<<<grid_for(S), kBlock, 0, st>>>(S, L.A.pdeg, L.A.tptr, L.A.otab);
+    }
+    {  // longest row, for kernels that stage a whole row
+        int32_t *dmax = tmp.get<int32_t>(1);
+        k_max_i32<<<1, kBlock, 0, st>>>(deg, n, dmax);
+        HIP_CHECK(hipMemcpyAsync(&L.max_row, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+    }
     L.A.n = n;
     L.A.nslices = S;
     L.A.nnz = nnz;
@@ -307,28 +422,22 @@ void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t 
     L.slotU = ar.get<int64_t>(nf);
     L.slotL = ar.get<int64_t>(nf);
     if (nf > 0) {
-        k_fill_upper<<<grid_for(nf), kBlock, 0, st>>>(nf, L.own, L.nb, L.ownStart, cntL,
-                                                     L.A.sptr, L.A.col, L.slotU);
+        const Slots slot{L.A.sptr, L.A.iperm, L.A.tptr, L.A.otab};
+        k_fill_upper<<<grid_for(nf), kBlock, 0, st>>>(nf, L.own, L.nb, L.ownStart, cntL, slot,
+                                                     L.A.col, L.slotU);
         int32_t *cursor = tmp.get<int32_t>(n);
         int64_t *faceAt = tmp.get<int64_t>(nnz);
         HIP_CHECK(hipMemsetAsync(cursor, 0, sizeof(int32_t) * n, st));
-        k_fill_lower<<<grid_for(nf), kBlock, 0, st>>>(nf, L.own, L.nb, L.A.sptr, cursor,
-                                                     L.A.col, faceAt);
-        k_sort_lower<<<grid_for(n), kBlock, 0, st>>>(n, L.A.sptr, cntL, L.A.col, faceAt,
-                                                    L.slotL);
+        k_fill_lower<<<grid_for(nf), kBlock, 0, st>>>(nf, L.own, L.nb, slot, cursor, L.A.col,
+                                                     faceAt);
+        k_sort_lower<<<grid_for(n), kBlock, 0, st>>>(n, slot, cntL, L.A.col, faceAt, L.slotL);
     }
-    k_fill_pad<<<grid_for(S * kWave), kBlock, 0, st>>>(n, S, L.A.sptr, L.ownStart, cntL,
-                                                      L.A.col, L.A.val, L.A.valT);
+    if (!L.A.pdeg)
+        k_fill_pad<<<grid_for(S * kWave), kBlock, 0, st>>>(n, S, L.A.sptr, deg, L.A.col, L.A.val,
+                                                          L.A.valT);
     HIP_CHECK(hipGetLastError());
     set_level_values(L, st);
-    // widest slice (informational, also bounds coarse-level rows)
-    std::vector<int64_t> hs(S + 1);
-    HIP_CHECK(hipMemcpyAsync(hs.data(), L.A.sptr, sizeof(int64_t) * (S + 1),
-                             hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));  // tmp is released after this point
-    int64_t mw = 0;
-    for (int64_t s = 0; s < S; ++s) mw = std::max(mw, (hs[s + 1] - hs[s]) / kWave);
-    L.A.maxw = (int)mw;
 }
 
 void set_level_values(Level &L, hipStream_t st) {

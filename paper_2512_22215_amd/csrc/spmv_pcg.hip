@@ -19,22 +19,29 @@
 namespace ldu {
 
 // ---------------------------------------------------------------- products
-template <typename T>
+template <bool CMP, typename T>
 __global__ void __launch_bounds__(kBlock) k_amul(SellView<T> A, const T *__restrict__ x,
                                                  T *__restrict__ y) {
     const int lane = threadIdx.x & 63;
     for_each_slice(A.nslices, [&](int64_t s) {
-        const int64_t i = s * kWave + lane;
-        if (i < A.n) y[i] = sell_row(A, s, lane, (int32_t)i, Direct<T>{x});
+        const int64_t p = s * kWave + lane;
+        if (p < A.n) {
+            const int32_t i = sv_row<CMP>(A, p);
+            y[i] = sell_row<CMP>(A, s, lane, i, Direct<T>{x});
+        }
     });
 }
 
 void launch_amul(const SellView<double> &A, const double *x, double *y, hipStream_t st) {
-    k_amul<double><<<stream_grid_slices(A.nslices), kBlock, 0, st>>>(A, x, y);
+    const int G = stream_grid_slices(A.nslices);
+    if (A.pdeg) k_amul<true, double><<<G, kBlock, 0, st>>>(A, x, y);
+    else k_amul<false, double><<<G, kBlock, 0, st>>>(A, x, y);
     HIP_CHECK(hipGetLastError());
 }
 void launch_amul32(const SellView<float> &A, const float *x, float *y, hipStream_t st) {
-    k_amul<float><<<stream_grid_slices(A.nslices), kBlock, 0, st>>>(A, x, y);
+    const int G = stream_grid_slices(A.nslices);
+    if (A.pdeg) k_amul<true, float><<<G, kBlock, 0, st>>>(A, x, y);
+    else k_amul<false, float><<<G, kBlock, 0, st>>>(A, x, y);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -86,7 +93,7 @@ void copy_history(ldu_t *h, ldu_stats *stats, int count, hipStream_t st) {
 //   kResCycle  : GAMG/refinement outer loop, honours and sets the done flag
 enum { kResPlain = 0, kResCycle = 1 };
 
-template <bool P, bool MAXABS>
+template <bool CMP, bool P, bool MAXABS>
 __global__ void __launch_bounds__(kBlock)
 k_residual(SellView<double> A, const double *__restrict__ b, const double *__restrict__ x,
            double *__restrict__ r, double *__restrict__ p, int precond, int gated,
@@ -95,10 +102,11 @@ k_residual(SellView<double> A, const double *__restrict__ b, const double *__res
     const int lane = threadIdx.x & 63;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // rr, bb, rho, maxabs
     for_each_slice(A.nslices, [&](int64_t s) {
-        const int64_t i = s * kWave + lane;
-        if (i < A.n) {
+        const int64_t pos = s * kWave + lane;
+        if (pos < A.n) {
+            const int32_t i = sv_row<CMP>(A, pos);
             const double bi = b[i];
-            const double ri = bi - sell_row(A, s, lane, (int32_t)i, Direct<double>{x});
+            const double ri = bi - sell_row<CMP>(A, s, lane, i, Direct<double>{x});
             r[i] = ri;
             acc[0] += ri * ri;
             acc[1] += bi * bi;
@@ -151,8 +159,12 @@ static void launch_residual(ldu_t *h, const SellView<double> &A, const double *b
                             double *r, double *p, int precond, int mode, bool write_hist,
                             hipStream_t st) {
     const int G = stream_grid_slices(A.nslices);
-    k_residual<P, MAXABS><<<G, kBlock, 0, st>>>(A, b, x, r, p, precond, mode == kResCycle,
-                                                h->partials, h->dev);
+    if (A.pdeg)
+        k_residual<true, P, MAXABS><<<G, kBlock, 0, st>>>(A, b, x, r, p, precond,
+                                                          mode == kResCycle, h->partials, h->dev);
+    else
+        k_residual<false, P, MAXABS><<<G, kBlock, 0, st>>>(A, b, x, r, p, precond,
+                                                           mode == kResCycle, h->partials, h->dev);
     launch_finalize<4, 1>(h->partials, G, h->dev,
                           EpiResidual{mode, write_hist ? 1 : 0, P ? 1 : 0, h->hist}, st);
     HIP_CHECK(hipGetLastError());
@@ -182,6 +194,7 @@ double residual_norm(ldu_t *h, const Level &L, bool tr, const double *b, const d
 
 // ---------------------------------------------------------------- PCG, FP64
 // q = A p and p.q -> alpha = rho / p.q
+template <bool CMP>
 __global__ void __launch_bounds__(kBlock)
 k_pcg_q(SellView<double> A, const double *__restrict__ p, double *__restrict__ q,
         double *partials, const DevScalars *ds) {
@@ -189,9 +202,10 @@ k_pcg_q(SellView<double> A, const double *__restrict__ p, double *__restrict__ q
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
     for_each_slice(A.nslices, [&](int64_t s) {
-        const int64_t i = s * kWave + lane;
-        if (i < A.n) {
-            const double qi = sell_row(A, s, lane, (int32_t)i, Direct<double>{p});
+        const int64_t pos = s * kWave + lane;
+        if (pos < A.n) {
+            const int32_t i = sv_row<CMP>(A, pos);
+            const double qi = sell_row<CMP>(A, s, lane, i, Direct<double>{p});
             q[i] = qi;
             acc[0] += p[i] * qi;
         }
@@ -215,7 +229,8 @@ struct EpiAlpha {
 
 void launch_pcg_q(ldu_t *h, const SellView<double> &A, const double *p, double *q, int grid,
                   hipStream_t st) {
-    k_pcg_q<<<grid, kBlock, 0, st>>>(A, p, q, h->partials, h->dev);
+    if (A.pdeg) k_pcg_q<true><<<grid, kBlock, 0, st>>>(A, p, q, h->partials, h->dev);
+    else k_pcg_q<false><<<grid, kBlock, 0, st>>>(A, p, q, h->partials, h->dev);
     launch_finalize<1>(h->partials, grid, h->dev, EpiAlpha{}, st);
 }
 
@@ -418,6 +433,7 @@ struct EpiMxStart {
     }
 };
 
+template <bool CMP>
 __global__ void __launch_bounds__(kBlock)
 k_mx_q(SellView<float> A, const float *__restrict__ p, float *__restrict__ q, double *partials,
        const DevScalars *ds) {
@@ -425,9 +441,10 @@ k_mx_q(SellView<float> A, const float *__restrict__ p, float *__restrict__ q, do
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
     for_each_slice(A.nslices, [&](int64_t s) {
-        const int64_t i = s * kWave + lane;
-        if (i < A.n) {
-            const float qi = sell_row(A, s, lane, (int32_t)i, Direct<float>{p});
+        const int64_t pos = s * kWave + lane;
+        if (pos < A.n) {
+            const int32_t i = sv_row<CMP>(A, pos);
+            const float qi = sell_row<CMP>(A, s, lane, i, Direct<float>{p});
             q[i] = qi;
             acc[0] += (double)p[i] * (double)qi;
         }
@@ -547,7 +564,10 @@ int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool 
         launch_finalize<2>(h->partials, G, h->dev, EpiMxStart{}, st);
         for (;;) {
             for (int k = 0; k < every; ++k) {
-                k_mx_q<<<G, kBlock, 0, st>>>(A32, h->p32, h->q32, h->partials, h->dev);
+                if (A32.pdeg)
+                    k_mx_q<true><<<G, kBlock, 0, st>>>(A32, h->p32, h->q32, h->partials, h->dev);
+                else
+                    k_mx_q<false><<<G, kBlock, 0, st>>>(A32, h->p32, h->q32, h->partials, h->dev);
                 launch_finalize<1>(h->partials, G, h->dev, EpiMxAlpha{}, st);
                 k_mx_update<<<G, kBlock, 0, st>>>(n, S, A32.diag, h->d32, h->r32, h->p32,
                                                   h->q32, h->partials, h->dev);

@@ -258,8 +258,9 @@ int orc_pcg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
 /*     r = b - A64 x                                                          */
 /* Inner CG: FP32 values, vectors, products and axpys; the dot products are  */
 /* accumulated in FP64 and alpha, beta are formed in FP64, then rounded to   */
-/* FP32 for the updates.  Stops at ||r||/||rhat|| <= inner_tol or after      */
-/* inner_max_iter iterations.                                                 */
+/* FP32 for the updates.  Stops at ||r||/||rhat|| <= max(inner_tol,          */
+/* 0.3 tol/res) (res: the outer relative residual) or after inner_max_iter   */
+/* iterations.                                                                */
 /* Pin: refinement converges to the FP64 solution (tests), FP32 Amul error   */
 /* bound.                                                                     */
 /* ------------------------------------------------------------------------ */
@@ -296,7 +297,8 @@ static void fmat_mul(const fmat *m, const float *x, float *y) {
     orc_amul_f32(m->n, m->nf, m->own, m->nb, m->diag, m->up, m->lo, x, y);
 }
 
-/* inner FP32 CG from d = 0 on A32 d = rhat; returns iterations done */
+/* inner FP32 CG from d = 0 on A32 d = rhat to ||r|| <= inner_tol ||rhat||;
+ * returns iterations done */
 static int pcg32_inner(const fmat *m, const float *rhat, float *d,
                        double inner_tol, int inner_max) {
     const int32_t n = m->n;
@@ -331,8 +333,16 @@ static int pcg32_inner(const fmat *m, const float *rhat, float *d,
     return it;
 }
 
-/* shared FP64 refinement driver; inner(ctx, rhat, d) fills d */
-typedef int (*inner_fn)(void *ctx, const float *rhat, float *d);
+/* shared FP64 refinement driver; inner(ctx, rhat, d, tol_now) fills d.
+ * tol_now = max(inner_tol, 0.3 tol / res): an inner solve stops once its
+ * relative reduction would bring the outer residual below tol with a safety
+ * factor of 0.3, or at the fixed inner tolerance, whichever is looser. */
+typedef int (*inner_fn)(void *ctx, const float *rhat, float *d, double tol_now);
+
+static double inner_target(double inner_tol, double tol, double res) {
+    double t = 0.3 * tol / res;
+    return t > inner_tol ? t : inner_tol;
+}
 
 static int refine(const omat *m, const double *b, double *x, double tol,
                   int max_refine, inner_fn inner, void *ctx, int *refinements,
@@ -360,7 +370,7 @@ static int refine(const omat *m, const double *b, double *x, double tol,
         double s = 0.0;
         for (int32_t i = 0; i < n; ++i) s = fabs(r[i]) > s ? fabs(r[i]) : s;
         for (int32_t i = 0; i < n; ++i) rhat[i] = (float)(r[i] / s);
-        int it = inner(ctx, rhat, d);
+        int it = inner(ctx, rhat, d, res);
         if (inner_total) *inner_total += it;
         for (int32_t i = 0; i < n; ++i) x[i] = x[i] + s * (double)d[i];
         ++k;
@@ -376,13 +386,14 @@ static int refine(const omat *m, const double *b, double *x, double tol,
 
 typedef struct {
     const fmat *m;
-    double tol;
+    double tol, outer_tol;
     int max_iter;
 } pcg32_ctx;
 
-static int pcg32_inner_cb(void *ctx, const float *rhat, float *d) {
+static int pcg32_inner_cb(void *ctx, const float *rhat, float *d, double res) {
     pcg32_ctx *c = (pcg32_ctx *)ctx;
-    return pcg32_inner(c->m, rhat, d, c->tol, c->max_iter);
+    return pcg32_inner(c->m, rhat, d, inner_target(c->tol, c->outer_tol, res),
+                       c->max_iter);
 }
 
 int orc_pcg_mixed(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
@@ -393,7 +404,7 @@ int orc_pcg_mixed(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
                   double *true_res) {
     omat m = make_mat(n, nf, own, nb, diag, upper, lower, transpose);
     fmat fm = make_fmat(&m);
-    pcg32_ctx c = {&fm, inner_tol, inner_max_iter};
+    pcg32_ctx c = {&fm, inner_tol, tol, inner_max_iter};
     int st = refine(&m, b, x, tol, max_refine, pcg32_inner_cb, &c, refinements,
                     inner_iters, hist, true_res);
     free_fmat(&fm);
@@ -1016,10 +1027,69 @@ typedef struct {
     vparams vp;
 } vc32_ctx;
 
-static int vcycle32_cb(void *ctx, const float *rhat, float *d) {
+static int vcycle32_cb(void *ctx, const float *rhat, float *d, double res) {
     vc32_ctx *c = (vc32_ctx *)ctx;
+    (void)res;
     vcycle32(c->h, 0, rhat, d, &c->vp);
     return 1;
+}
+
+/* inner FP32 CG preconditioned by one FP32 V-cycle (scaling off), from d = 0
+ * on A32 d = rhat; FP64 dot products, alpha and beta rounded to FP32 */
+typedef struct {
+    const orc_gamg *h;
+    vparams vp;
+    double tol, outer_tol;
+    int max_iter;
+} vpc32_ctx;
+
+static int pcg32_vcycle_inner(void *ctx, const float *rhat, float *d, double res) {
+    vpc32_ctx *c = (vpc32_ctx *)ctx;
+    const double tol_now = inner_target(c->tol, c->outer_tol, res);
+    fmat m;
+    level_fmat(&c->h->lev[0], c->vp.transpose, &m);
+    const int32_t n = m.n;
+    float *r = xcalloc(n, sizeof(float));
+    float *z = xcalloc(n, sizeof(float));
+    float *p = xcalloc(n, sizeof(float));
+    float *q = xcalloc(n, sizeof(float));
+    for (int32_t i = 0; i < n; ++i) { d[i] = 0.0f; r[i] = rhat[i]; }
+    double r0 = sqrt(dot_f32(n, r, r));
+    int it = 0;
+    if (r0 > 0.0) {
+        vcycle32(c->h, 0, r, z, &c->vp);
+        for (int32_t i = 0; i < n; ++i) p[i] = z[i];
+        double rho = dot_f32(n, r, z);
+        while (it < c->max_iter) {
+            fmat_mul(&m, p, q);
+            double pq = dot_f32(n, p, q);
+            if (!isfinite(pq) || fabs(pq) <= 1e-300) break;
+            float af = (float)(rho / pq);
+            for (int32_t i = 0; i < n; ++i) d[i] = d[i] + af * p[i];
+            for (int32_t i = 0; i < n; ++i) r[i] = r[i] - af * q[i];
+            ++it;
+            if (sqrt(dot_f32(n, r, r)) <= tol_now * r0) break;
+            vcycle32(c->h, 0, r, z, &c->vp);
+            double rho_new = dot_f32(n, r, z);
+            float bf = (float)(rho_new / rho);
+            rho = rho_new;
+            for (int32_t i = 0; i < n; ++i) p[i] = z[i] + bf * p[i];
+        }
+    }
+    free(r); free(z); free(p); free(q);
+    return it;
+}
+
+int orc_pcg_gamg_mixed(const orc_gamg *h, const double *b, double *x, double tol,
+                       int max_refine, double inner_tol, int inner_max_iter,
+                       int n_pre, int n_post, double omega, int transpose,
+                       int *refinements, int *inner_iters, double *hist,
+                       double *true_res) {
+    omat m = level_mat(&h->lev[0], transpose);
+    vpc32_ctx c = {h, {n_pre, n_post, 0, transpose, omega}, inner_tol, tol,
+                   inner_max_iter};
+    return refine(&m, b, x, tol, max_refine, pcg32_vcycle_inner, &c, refinements,
+                  inner_iters, hist, true_res);
 }
 
 int orc_gamg_mixed(const orc_gamg *h, const double *b, double *x, double tol,

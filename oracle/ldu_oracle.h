@@ -101,6 +101,12 @@ int orc_gamg_solve(const orc_gamg *h, const double *b, double *x, double tol,
 int orc_pcg_gamg(const orc_gamg *h, const double *b, double *x, double tol,
                  int max_iter, int n_pre, int n_post, double omega,
                  int transpose, int *iters, double *hist, double *true_res);
+/* FP64 refinement around an inner FP32 CG preconditioned by an FP32 V-cycle */
+int orc_pcg_gamg_mixed(const orc_gamg *h, const double *b, double *x, double tol,
+                       int max_refine, double inner_tol, int inner_max_iter,
+                       int n_pre, int n_post, double omega, int transpose,
+                       int *refinements, int *inner_iters, double *hist,
+                       double *true_res);
 /* FP32 V-cycle (coarsest level in FP64) inside FP64 refinement */
 int orc_gamg_mixed(const orc_gamg *h, const double *b, double *x, double tol,
                    int max_refine, int n_pre, int n_post, double omega,

@@ -90,6 +90,8 @@ def lib():
                                  C.c_int, C.c_int, ip, _f64o, dp]
     L.orc_pcg_gamg.argtypes = [vp, _f64p, _f64p, d, C.c_int, C.c_int, C.c_int, d,
                                C.c_int, ip, _f64o, dp]
+    L.orc_pcg_gamg_mixed.argtypes = [vp, _f64p, _f64p, d, C.c_int, d, C.c_int, C.c_int,
+                                     C.c_int, d, C.c_int, ip, ip, _f64o, dp]
     L.orc_gamg_mixed.argtypes = [vp, _f64p, _f64p, d, C.c_int, C.c_int, C.c_int, d,
                                  C.c_int, C.c_int, ip, _f64o, dp]
     L.orc_coeff_grad.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p,
@@ -280,6 +282,23 @@ class Gamg:
                                 float(omega), int(bool(transpose)), C.byref(k),
                                 hist, C.byref(tr))
         return SolveResult(st, x, k.value, hist[: k.value + 1].copy(), tr.value)
+
+    def pcg_mixed(self, b, x0=None, tol=1e-8, max_refine=50, inner_tol=1e-4,
+                  inner_max_iter=1000, n_pre=2, n_post=2, omega=0.75,
+                  transpose=False):
+        """FP64 refinement around FP32 CG preconditioned by an FP32 V-cycle."""
+        x = np.zeros(self.A.n) if x0 is None else _c(x0, np.float64).copy()
+        hist = np.zeros(max_refine + 2)
+        k = C.c_int(0)
+        inner = C.c_int(0)
+        tr = C.c_double(0.0)
+        st = lib().orc_pcg_gamg_mixed(self._h, _c(b, np.float64), x, float(tol),
+                                      int(max_refine), float(inner_tol),
+                                      int(inner_max_iter), int(n_pre), int(n_post),
+                                      float(omega), int(bool(transpose)),
+                                      C.byref(k), C.byref(inner), hist, C.byref(tr))
+        return SolveResult(st, x, k.value, hist[: k.value + 1].copy(), tr.value,
+                           inner.value)
 
     def solve_mixed(self, b, x0=None, tol=1e-8, max_refine=200, n_pre=2,
                     n_post=2, omega=0.75, scale=True, transpose=False):

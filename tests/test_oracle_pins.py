@@ -579,3 +579,14 @@ def test_set_values_equals_fresh_galerkin_on_same_aggregation():
         ref = P.T @ Af @ P
         assert np.allclose(Ac, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
         Af = Ac
+
+
+def test_mixed_vcycle_pcg_refines_to_fp64_solution():
+    c = _perm_case(box_case(9, 8, 7, coeff="lognormal", sigma=1.0,
+                            dirichlet_x0=1.0, seed=45), 46)
+    g = O.Gamg(O.Ldu.from_case(c), n_coarsest=10)
+    xd = np.linalg.solve(dense_case(c), c.rhs[0])
+    r = g.pcg_mixed(c.rhs[0], tol=1e-12, n_pre=1, n_post=1)
+    assert r.status == O.OK and r.true_residual <= 1e-12
+    assert np.linalg.norm(r.x - xd) <= 1e-10 * np.linalg.norm(xd)
+    assert r.iterations <= 6

@@ -68,14 +68,15 @@ typedef struct {
     double abs_tol;       /* unused, reserved: must be 0 */
     int max_iter;         /* FP64: CG iterations; MIXED: per inner solve cap is inner_max_iter */
     int check_every;      /* host reads the convergence flag every k iterations (>= 1) */
-    int precond;          /* 0 none, 1 diagonal, 2 one GAMG V-cycle (FP64 only; the
-                             handle's hierarchy and sweep settings from gamg_setup, or
-                             the defaults; correction scaling off so that the
-                             preconditioner is symmetric) */
+    int precond;          /* 0 none, 1 diagonal, 2 one GAMG V-cycle (the handle's
+                             hierarchy and sweep settings from gamg_setup, or the
+                             defaults; correction scaling off so that the
+                             preconditioner is symmetric; FP32 V-cycle in MIXED) */
     int precision;        /* LDU_FP64 or LDU_MIXED */
     int max_refine;       /* MIXED: outer refinement steps */
     int inner_max_iter;   /* MIXED: FP32 CG iterations per refinement */
-    double inner_rel_tol; /* MIXED: inner stop at ||r32||/||rhat|| <= this */
+    double inner_rel_tol; /* MIXED: inner stop at ||r32||/||rhat|| <= max(this,
+                             0.3 rel_tol / current outer residual) */
 } ldu_pcg_opts;
 
 /* Options of gamg_setup / gamg_solve.  Defaults (ldu_gamg_default_opts):

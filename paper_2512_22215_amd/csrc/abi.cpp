@@ -72,7 +72,7 @@ hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 void check_pcg_opts(const ldu_pcg_opts &o) {
     if (!(o.rel_tol >= 0.0) || o.abs_tol != 0.0 || o.max_iter < 0 || o.check_every < 1 ||
-        o.precond < 0 || o.precond > 2 || (o.precond == 2 && o.precision != LDU_FP64) ||
+        o.precond < 0 || o.precond > 2 ||
         (o.precision != LDU_FP64 && o.precision != LDU_MIXED) || o.max_refine < 0 ||
         o.inner_max_iter < 1 || !(o.inner_rel_tol > 0.0))
         throw Error(LDU_ERR_ARG, "invalid ldu_pcg_opts");
@@ -271,15 +271,16 @@ static int pcg_common(ldu_handle h, const double *b, double *x, const ldu_pcg_op
         if (opts) o = *opts;
         check_pcg_opts(o);
         hipStream_t st = S(hip_stream);
-        if (o.precision == LDU_MIXED) return pcg_mixed(h, b, x, o, tr, stats, st);
         if (o.precond == 2) {
             if (!h->gamg_ready) {
                 ldu_gamg_opts go;
                 ldu_gamg_default_opts(&go);
                 gamg_build(h, go, st);
             }
+            if (o.precision == LDU_MIXED) return pcg_gamg_mixed(h, b, x, o, tr, stats, st);
             return pcg_gamg_fp64(h, b, x, o, tr, stats, st);
         }
+        if (o.precision == LDU_MIXED) return pcg_mixed(h, b, x, o, tr, stats, st);
         return pcg_fp64(h, b, x, o, tr, stats, st);
     });
 }

@@ -260,6 +260,10 @@ __global__ void k_singular(Sell A, int *flag) {
     }
 }
 
+// V-cycle kernels stop once the outer solve finished or the inner solve of
+// the mixed preconditioned CG converged (inner_done is 0 in FP64 solves)
+__device__ __forceinline__ bool vc_skip(const DevScalars *ds) { return ds->done || ds->inner_done; }
+
 // ---------------------------------------------------------------- setup
 // FP32 copies of every level's values; level 0's live with the handle
 static void ensure_f32_levels(ldu_t *h, hipStream_t st) {
@@ -413,7 +417,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_first(int32_t n, int64_t S, const T *__restrict__ r, const T *__restrict__ D,
            T *__restrict__ e, T omega, const DevScalars *ds) {
-    if (ds->done) return;
+    if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
@@ -424,7 +428,7 @@ k_vc_first(int32_t n, int64_t S, const T *__restrict__ r, const T *__restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_zero(int32_t n, int64_t S, T *__restrict__ e, const DevScalars *ds) {
-    if (ds->done) return;
+    if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
@@ -437,7 +441,7 @@ template <bool CMP, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
             T *__restrict__ eo, T omega, const DevScalars *ds) {
-    if (ds->done) return;
+    if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     for_each_slice(A.nslices, [&](int64_t s) {
         const int64_t p = s * kWave + lane;
@@ -454,7 +458,7 @@ template <bool CMP, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_resid(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
            T *__restrict__ t, const DevScalars *ds) {
-    if (ds->done) return;
+    if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     for_each_slice(A.nslices, [&](int64_t s) {
         const int64_t p = s * kWave + lane;
@@ -470,7 +474,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_restrict(int32_t nc, const int32_t *__restrict__ start, const int32_t *__restrict__ cells,
               const T *__restrict__ t, T *__restrict__ rc, const DevScalars *ds) {
-    if (ds->done) return;
+    if (vc_skip(ds)) return;
     GRID_STRIDE(a, nc) {
         T s = T(0);
         for (int32_t k = start[a]; k < start[a + 1]; ++k) s += t[cells[k]];
@@ -483,7 +487,7 @@ template <bool CMP, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_scale(SellView<T> A, const T *__restrict__ ec, const int32_t *__restrict__ agg,
            const T *__restrict__ t, double *partials, const DevScalars *ds) {
-    if (ds->done) return;
+    if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     double acc[2] = {0.0, 0.0};
     for_each_slice(A.nslices, [&](int64_t s) {
@@ -500,7 +504,7 @@ k_vc_scale(SellView<T> A, const T *__restrict__ ec, const int32_t *__restrict__ 
 }
 
 struct EpiScale {
-    __device__ bool active(const DevScalars *ds) const { return !ds->done; }
+    __device__ bool active(const DevScalars *ds) const { return !ds->done && !ds->inner_done; }
     __device__ void operator()(const double *v, DevScalars *ds) const {
         ds->s = (isfinite(v[1]) && fabs(v[1]) > 1e-300) ? v[0] / v[1] : 1.0;
     }
@@ -511,7 +515,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_correct(int32_t n, int64_t S, const T *__restrict__ ec, const int32_t *__restrict__ agg,
              T *__restrict__ e, int use_s, const DevScalars *ds) {
-    if (ds->done) return;
+    if (vc_skip(ds)) return;
     const T sc = use_s ? (T)ds->s : T(1);
     const int lane = threadIdx.x & 63;
     for_each_slice(S, [&](int64_t s) {
@@ -633,7 +637,7 @@ k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
     __shared__ int32_t cL[kWaveRow * kWave];
     __shared__ double vL[kWaveRow * kWave];
     __shared__ double p[kWave];
-    if (ds->done) return;
+    if (vc_skip(ds)) return;
     const int32_t n = A.n;
     const int i = threadIdx.x;
     double di = 1.0, ri = 0.0;
@@ -696,7 +700,7 @@ __global__ void __launch_bounds__(kBlock)
 k_coarsest(SellView<double> A, const TI *__restrict__ rhs, TI *__restrict__ eo,
            double *__restrict__ w, int singular, double tol, int max_it, const DevScalars *ds) {
     extern __shared__ double lds_w[];
-    if (ds->done) return;
+    if (vc_skip(ds)) return;
     coarsest_body<TI, NW>(A, rhs, eo, A.n <= kLdsCoarse ? lds_w : w, singular, tol, max_it);
 }
 
@@ -1057,6 +1061,166 @@ int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, b
     if (stats) {
         stats->iterations = hs.iters;
         stats->final_residual = res;
+        stats->converged = (status == LDU_OK);
+    }
+    copy_history(h, stats, hs.iters + 1, st);
+    return status;
+}
+
+// FP32 inner CG preconditioned by an FP32 V-cycle (FP64 coarsest), inside FP64
+// refinement; inner dot products in FP64, alpha/beta rounded to FP32
+
+// rhat = fp32(r / ||r||_inf), d = 0; ||rhat||^2
+__global__ void __launch_bounds__(kBlock)
+k_mxg_start(int32_t n, int64_t S, const double *__restrict__ r, float *__restrict__ r32,
+            float *__restrict__ d32, double *partials, const DevScalars *ds) {
+    if (ds->done) return;
+    const double sc = ds->maxabs;
+    const int lane = threadIdx.x & 63;
+    double acc[2] = {0.0, 0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            const float ri = (float)(r[i] / sc);
+            r32[i] = ri;
+            d32[i] = 0.0f;
+            acc[0] += (double)ri * (double)ri;
+        }
+    });
+    block_partials<2>(acc, partials);
+}
+
+// p = z; rho = r.z (FP32 vectors, FP64 sum)
+__global__ void __launch_bounds__(kBlock)
+k_mxg_p0(int32_t n, int64_t S, const float *__restrict__ r, const float *__restrict__ z,
+         float *__restrict__ p, double *partials, const DevScalars *ds) {
+    if (ds->done || ds->inner_done) return;
+    const int lane = threadIdx.x & 63;
+    double acc[1] = {0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            p[i] = z[i];
+            acc[0] += (double)r[i] * (double)z[i];
+        }
+    });
+    block_partials<1>(acc, partials);
+}
+
+struct EpiMxRho {
+    __device__ bool active(const DevScalars *ds) const { return !(ds->done || ds->inner_done); }
+    __device__ void operator()(const double *t, DevScalars *ds) const { ds->rho = t[0]; }
+};
+
+// rho' = r.z -> beta (FP64), then p = z + fp32(beta) p in the next kernel
+__global__ void __launch_bounds__(kBlock)
+k_mxg_rz(int32_t n, int64_t S, const float *__restrict__ r, const float *__restrict__ z,
+         double *partials, const DevScalars *ds) {
+    if (ds->done || ds->inner_done) return;
+    const int lane = threadIdx.x & 63;
+    double acc[1] = {0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) acc[0] += (double)r[i] * (double)z[i];
+    });
+    block_partials<1>(acc, partials);
+}
+
+struct EpiMxBeta {
+    __device__ bool active(const DevScalars *ds) const { return !(ds->done || ds->inner_done); }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
+        ds->beta = t[0] / ds->rho;
+        ds->rho = t[0];
+    }
+};
+
+__global__ void __launch_bounds__(kBlock)
+k_mxg_p(int32_t n, int64_t S, const float *__restrict__ z, float *__restrict__ p,
+        const DevScalars *ds) {
+    if (ds->done || ds->inner_done) return;
+    const float bf = (float)ds->beta;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) p[i] = z[i] + bf * p[i];
+    });
+}
+
+struct EpiMxgStart {
+    __device__ bool active(const DevScalars *ds) const { return !ds->done; }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
+        ds->scale = ds->maxabs;
+        ds->r0 = sqrt(t[0]);
+        ds->inner_iters = 0;
+        ds->inner_done = !(ds->r0 > 0.0);
+        const double target = 0.3 * ds->tol / ds->res;
+        ds->inner_now = target > ds->inner_tol ? target : ds->inner_tol;
+    }
+};
+
+int pcg_gamg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
+                   ldu_stats *stats, hipStream_t st) {
+    ensure_work32(h, st);
+    ldu_gamg_opts go = h->gamg_opts;
+    go.scale_correction = 0;
+    Level &L = h->levels[0];
+    const SellView<double> A = L.A.view(tr);
+    const SellView<float> A32 = L.A.view32(tr);
+    const int n = L.n;
+    const int64_t S = L.A.nslices;
+    const int G = stream_grid_slices(S);
+    ensure_hist(h, o.max_refine + 2);
+    fill_level_stats(h, stats);
+    if (stats) stats->history_count = 0;
+    set_scalars_for_solve(h, o.rel_tol, o.max_refine, st);
+    set_inner(h, o.inner_rel_tol, o.inner_max_iter, st);
+    VCtx c = make_ctx(h, go, tr, st);
+    launch_residual_cycle(h, A, b, x, h->r, true, G, st);
+    read_scalars(h, st);
+    DevScalars &hs = *h->host;
+    if (stats) stats->initial_residual = hs.res;
+    if (hs.bnorm == 0.0) {
+        zero_vector(x, n, st);
+        if (stats) {
+            stats->iterations = 0;
+            stats->refinements = 0;
+            stats->converged = 1;
+            stats->initial_residual = stats->final_residual = 0.0;
+        }
+        copy_history(h, stats, 1, st);
+        return LDU_OK;
+    }
+    const int every = o.check_every > 0 ? o.check_every : 16;
+    long long inner_total = 0;
+    while (hs.done == kRunning) {
+        k_mxg_start<<<G, kBlock, 0, st>>>(n, S, h->r, h->r32, h->d32, h->partials, h->dev);
+        launch_finalize<2>(h->partials, G, h->dev, EpiMxgStart{}, st);
+        const float *z = vcycle<float>(c, 0, h->r32);
+        k_mxg_p0<<<G, kBlock, 0, st>>>(n, S, h->r32, z, h->p32, h->partials, h->dev);
+        launch_finalize<1>(h->partials, G, h->dev, EpiMxRho{}, st);
+        for (;;) {
+            for (int k = 0; k < every; ++k) {
+                launch_mx_q(h, A32, G, st);
+                launch_mx_update_plain(h, n, S, G, st);
+                z = vcycle<float>(c, 0, h->r32);
+                k_mxg_rz<<<G, kBlock, 0, st>>>(n, S, h->r32, z, h->partials, h->dev);
+                launch_finalize<1>(h->partials, G, h->dev, EpiMxBeta{}, st);
+                k_mxg_p<<<G, kBlock, 0, st>>>(n, S, z, h->p32, h->dev);
+            }
+            HIP_CHECK(hipGetLastError());
+            read_scalars(h, st);
+            if (hs.inner_done) break;
+        }
+        inner_total += hs.inner_iters;
+        launch_mx_refine(h, x, n, S, G, st);
+        launch_residual_cycle(h, A, b, x, h->r, true, G, st);
+        read_scalars(h, st);
+    }
+    const int status = finish_status(hs);
+    if (stats) {
+        stats->iterations = (int)inner_total;
+        stats->refinements = hs.iters;
+        stats->final_residual = hs.res;
         stats->converged = (status == LDU_OK);
     }
     copy_history(h, stats, hs.iters + 1, st);

@@ -75,6 +75,7 @@ struct DevScalars {
     double maxabs, scale;       // mixed: ||r||_inf of the outer residual
     double r0, inner_tol;       // mixed inner CG
     double s;                   // GAMG correction scaling factor
+    double inner_now;           // mixed: current inner tolerance
     double mean;                // coarsest: rhs mean
     int iters, max_iter, done, status;
     int inner_iters, inner_max, inner_done, pad_;
@@ -230,5 +231,11 @@ void gamg_vcycle64(ldu_t *h, const double *r, double *e, const ldu_gamg_opts &o,
                    bool tr, hipStream_t st);
 int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
                   ldu_stats *stats, hipStream_t st);
+int pcg_gamg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
+                   ldu_stats *stats, hipStream_t st);
+void launch_mx_q(ldu_t *h, const SellView<float> &A32, int G, hipStream_t st);
+void launch_mx_update_plain(ldu_t *h, int32_t n, int64_t S, int G, hipStream_t st);
+void set_inner(ldu_t *h, double inner_tol, int inner_max, hipStream_t st);
+void launch_mx_refine(ldu_t *h, double *x, int32_t n, int64_t S, int G, hipStream_t st);
 
 }  // namespace ldu

@@ -422,14 +422,19 @@ k_mx_start(int32_t n, int64_t S, const double *__restrict__ r, const float *__re
     block_partials<2>(acc, partials);
 }
 
+// start of an inner solve: ||rhat||, rho, and the inner target
+// max(inner_tol, 0.3 tol / res) for the current outer residual res
 struct EpiMxStart {
+    int has_rho;
     __device__ bool active(const DevScalars *ds) const { return !ds->done; }
     __device__ void operator()(const double *t, DevScalars *ds) const {
         ds->scale = ds->maxabs;
         ds->r0 = sqrt(t[0]);
-        ds->rho = t[1];
+        if (has_rho) ds->rho = t[1];
         ds->inner_iters = 0;
         ds->inner_done = !(ds->r0 > 0.0);
+        const double target = 0.3 * ds->tol / ds->res;
+        ds->inner_now = target > ds->inner_tol ? target : ds->inner_tol;
     }
 };
 
@@ -461,6 +466,7 @@ struct EpiMxAlpha {
     }
 };
 
+template <bool DIAGZ>
 __global__ void __launch_bounds__(kBlock)
 k_mx_update(int32_t n, int64_t S, const float *__restrict__ D, float *__restrict__ d,
             float *__restrict__ r, const float *__restrict__ p, const float *__restrict__ q,
@@ -476,22 +482,25 @@ k_mx_update(int32_t n, int64_t S, const float *__restrict__ D, float *__restrict
             const float ri = r[i] - af * q[i];
             d[i] = di;
             r[i] = ri;
-            const float zi = ri / D[i];
             acc[0] += (double)ri * (double)ri;
-            acc[1] += (double)ri * (double)zi;
+            if (DIAGZ) {
+                const float zi = ri / D[i];
+                acc[1] += (double)ri * (double)zi;
+            }
         }
     });
     block_partials<2>(acc, partials);
 }
 
 struct EpiMxInner {
+    int with_beta;
     __device__ bool active(const DevScalars *ds) const { return !(ds->done || ds->inner_done); }
     __device__ void operator()(const double *t, DevScalars *ds) const {
         const int it = ds->inner_iters + 1;
         ds->inner_iters = it;
-        if (sqrt(t[0]) <= ds->inner_tol * ds->r0 || it >= ds->inner_max) {
+        if (sqrt(t[0]) <= ds->inner_now * ds->r0 || it >= ds->inner_max) {
             ds->inner_done = 1;
-        } else {
+        } else if (with_beta) {
             ds->beta = t[1] / ds->rho;
             ds->rho = t[1];
         }
@@ -510,6 +519,20 @@ k_mx_p(int32_t n, int64_t S, const float *__restrict__ D, const float *__restric
     });
 }
 
+void launch_mx_q(ldu_t *h, const SellView<float> &A32, int G, hipStream_t st) {
+    if (A32.pdeg) k_mx_q<true><<<G, kBlock, 0, st>>>(A32, h->p32, h->q32, h->partials, h->dev);
+    else k_mx_q<false><<<G, kBlock, 0, st>>>(A32, h->p32, h->q32, h->partials, h->dev);
+    launch_finalize<1>(h->partials, G, h->dev, EpiMxAlpha{}, st);
+}
+
+// d += alpha p; r -= alpha q; ||r||^2 and the inner convergence test (the
+// preconditioned direction comes from outside)
+void launch_mx_update_plain(ldu_t *h, int32_t n, int64_t S, int G, hipStream_t st) {
+    k_mx_update<false><<<G, kBlock, 0, st>>>(n, S, nullptr, h->d32, h->r32, h->p32, h->q32,
+                                             h->partials, h->dev);
+    launch_finalize<2>(h->partials, G, h->dev, EpiMxInner{0}, st);
+}
+
 // x += s * fp64(d)
 __global__ void __launch_bounds__(kBlock)
 k_mx_refine(int32_t n, int64_t S, const float *__restrict__ d, double *__restrict__ x,
@@ -526,6 +549,12 @@ k_mx_refine(int32_t n, int64_t S, const float *__restrict__ d, double *__restric
 __global__ void k_mx_set_inner(DevScalars *ds, double inner_tol, int inner_max) {
     ds->inner_tol = inner_tol;
     ds->inner_max = inner_max;
+}
+void set_inner(ldu_t *h, double inner_tol, int inner_max, hipStream_t st) {
+    k_mx_set_inner<<<1, 1, 0, st>>>(h->dev, inner_tol, inner_max);
+}
+void launch_mx_refine(ldu_t *h, double *x, int32_t n, int64_t S, int G, hipStream_t st) {
+    k_mx_refine<<<G, kBlock, 0, st>>>(n, S, h->d32, x, h->dev);
 }
 
 int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
@@ -561,7 +590,7 @@ int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool 
     while (hs.done == kRunning) {
         k_mx_start<<<G, kBlock, 0, st>>>(n, S, h->r, A32.diag, h->r32, h->d32, h->p32,
                                          h->partials, h->dev);
-        launch_finalize<2>(h->partials, G, h->dev, EpiMxStart{}, st);
+        launch_finalize<2>(h->partials, G, h->dev, EpiMxStart{1}, st);
         for (;;) {
             for (int k = 0; k < every; ++k) {
                 if (A32.pdeg)
@@ -569,9 +598,9 @@ int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool 
                 else
                     k_mx_q<false><<<G, kBlock, 0, st>>>(A32, h->p32, h->q32, h->partials, h->dev);
                 launch_finalize<1>(h->partials, G, h->dev, EpiMxAlpha{}, st);
-                k_mx_update<<<G, kBlock, 0, st>>>(n, S, A32.diag, h->d32, h->r32, h->p32,
-                                                  h->q32, h->partials, h->dev);
-                launch_finalize<2>(h->partials, G, h->dev, EpiMxInner{}, st);
+                k_mx_update<true><<<G, kBlock, 0, st>>>(n, S, A32.diag, h->d32, h->r32,
+                                                        h->p32, h->q32, h->partials, h->dev);
+                launch_finalize<2>(h->partials, G, h->dev, EpiMxInner{1}, st);
                 k_mx_p<<<G, kBlock, 0, st>>>(n, S, A32.diag, h->r32, h->p32, h->dev);
             }
             HIP_CHECK(hipGetLastError());

@@ -209,14 +209,21 @@ def test_gamg_solve_matches_oracle(name):
     assert true_res(c, x.cpu().numpy()) <= 1e-8
 
 
-@pytest.mark.parametrize("solver", ["pcg", "gamg"])
+@pytest.mark.parametrize("solver", ["pcg", "gamg", "pcg_gamg"])
 def test_mixed_refines_to_fp64(solver):
     c = _gamg_case("c5s") if solver == "gamg" else CASES["ragged"]
+    if solver == "pcg_gamg":
+        c = _gamg_case("c3p")
     m = _lib().from_case(c)
     A = O.Ldu.from_case(c)
     if solver == "pcg":
         x, st = m.pcg(_t(c.rhs[0]), rel_tol=1e-12, precision="mixed")
         ref = O.pcg(A, c.rhs[0], tol=1e-12)
+    elif solver == "pcg_gamg":
+        x, st = m.pcg(_t(c.rhs[0]), rel_tol=1e-12, precision="mixed", precond=2)
+        ref = O.pcg(A, c.rhs[0], tol=1e-12, max_iter=20000)
+        orc = O.Gamg(A).pcg_mixed(c.rhs[0], tol=1e-12)
+        assert st.refinements == orc.iterations
     else:
         x, st = m.gamg(_t(c.rhs[0]), rel_tol=1e-12, precision="mixed")
         ref = O.Gamg(A).solve(c.rhs[0], tol=1e-12)

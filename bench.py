@@ -50,7 +50,9 @@ def log(*a):
 
 def amul_bytes(n, nf):
     """Algorithmic bytes of one FP64 Amul: diag, x, y (8 B each per cell) and
-    upper, lower (8 B each) plus owner/neighbour addressing (4 B each) per face."""
+    upper, lower (8 B each) plus owner/neighbour addressing (4 B each) per face.
+    The coefficient gradient moves the same count: lambda, x, g_diag per cell;
+    owner, neighbour, g_upper, g_lower per face."""
     return 24 * n + 24 * nf
 
 
@@ -194,7 +196,46 @@ def main():
     assert st.converged and res <= 1e-8, (st, res)
     t_step = float(np.mean(times))
 
+    # the mixed form of the same solve: FP64 refinement around FP32 CG with an
+    # FP32 V-cycle preconditioner (one warm-up, then the same step count)
+    mopts = dict(opts, precision="mixed")
+    m.pcg(b, **mopts)
+    mtimes = []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xm, sm = m.pcg(b, **mopts)
+        torch.cuda.synchronize()
+        mtimes.append(time.perf_counter() - t0)
+    mres = m.residual(b, xm)
+    assert sm.converged and mres <= 1e-8, (sm, mres)
+    log(f"[bench] mixed: {np.mean(mtimes):.4f} s, {sm.refinements} refinements, "
+        f"{sm.iterations} inner iterations, true residual {mres:.3e}")
+
+    # the adjoint form: lambda = A^-T (x - x_t) with the same preconditioned CG
+    # (on the transposed values of every level), then the per-face gradients
+    xt = torch.randn(case.n_cells, dtype=torch.float64, device=dev,
+                     generator=torch.Generator(device=dev).manual_seed(4))
+    g = xs - xt
+    m.adjoint(g, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, sa = m.adjoint(g, **opts)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    gd, gu, gl = m.coeff_grad(lam, xs)
+    t_grad = time_kernel(lambda: m.coeff_grad(lam, xs), 20, torch)
+    assert sa.converged
+    log(f"[bench] adjoint: {t_adj:.4f} s, {sa.iterations} iterations; coeff_grad "
+        f"{t_grad * 1e6:.0f} us")
+
     extra = {
+        "adjoint": {"solve_s": t_adj, "iterations": sa.iterations,
+                    "coeff_grad_us": t_grad * 1e6,
+                    "coeff_grad_GBps": amul_bytes(case.n_cells, case.n_faces) / t_grad / 1e9},
+        "mixed_solve": {"s": float(np.mean(mtimes)), "refinements": sm.refinements,
+                        "inner_iterations": sm.iterations, "true_residual": mres,
+                        "solver": "FP64 refinement, FP32 CG + FP32 V-cycle (FP64 coarsest)"},
         "setup_s": {"ldu_create": t_create, "gamg_setup": t_setup},
         "levels": nlev,
         "iterations": st.iterations,

@@ -82,7 +82,7 @@ typedef struct {
 /* Options of gamg_setup / gamg_solve.  Defaults (ldu_gamg_default_opts):
  * rel_tol 1e-8, max_cycles 200, n_coarsest 50, n_pre 2, n_post 2,
  * max_levels 50, scale_correction 1, match_rounds 16, precision LDU_FP64,
- * max_refine 200, omega 0.75. */
+ * max_refine 200, omega 0.75, passes 1. */
 typedef struct {
     double rel_tol;
     double abs_tol;        /* unused, reserved: must be 0 */
@@ -95,6 +95,12 @@ typedef struct {
     int precision;         /* LDU_FP64 or LDU_MIXED */
     int max_refine;        /* MIXED: refinement steps (one FP32 V-cycle each) */
     double omega;          /* Jacobi relaxation factor */
+    int passes;            /* pairwise matching passes per level (1..3): pass k
+                            * matches the aggregates of pass k-1 on their
+                            * Galerkin matrix, so aggregates hold up to about
+                            * 2^passes cells and the hierarchy has fewer levels
+                            * (aggressive agglomeration, the remedy the paper
+                            * points to for GAMG's many tiny levels, Sec. 4.4) */
 } ldu_gamg_opts;
 
 typedef struct {

@@ -82,14 +82,14 @@ void check_gamg_opts(const ldu_gamg_opts &o) {
     if (!(o.rel_tol >= 0.0) || o.abs_tol != 0.0 || o.max_cycles < 0 || o.n_coarsest < 1 ||
         o.n_pre < 0 || o.n_post < 0 || o.max_levels < 1 || o.max_levels > kMaxLevels ||
         o.match_rounds < 0 || (o.precision != LDU_FP64 && o.precision != LDU_MIXED) ||
-        o.max_refine < 0 || !(o.omega > 0.0) ||
+        o.max_refine < 0 || !(o.omega > 0.0) || o.passes < 1 || o.passes > 3 ||
         (o.scale_correction != 0 && o.scale_correction != 1))
         throw Error(LDU_ERR_ARG, "invalid ldu_gamg_opts");
 }
 
 bool same_structure(const ldu_gamg_opts &a, const ldu_gamg_opts &b) {
     return a.n_coarsest == b.n_coarsest && a.max_levels == b.max_levels &&
-           a.match_rounds == b.match_rounds;
+           a.match_rounds == b.match_rounds && a.passes == b.passes;
 }
 
 void ensure_gamg(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
@@ -131,6 +131,7 @@ void ldu_gamg_default_opts(ldu_gamg_opts *o) {
     o->precision = LDU_FP64;
     o->max_refine = 200;
     o->omega = 0.75;
+    o->passes = 1;
 }
 
 const char *ldu_last_error(void) { return g_last_error.c_str(); }

@@ -299,8 +299,30 @@ static void detect_singular(ldu_t *h, Level &L, hipStream_t st) {
     L.singular = (*h->hflag != 0) && L.n > 0;
 }
 
-// agglomerate level F; returns the number of aggregates
-static int32_t agglomerate(ldu_t *h, Level &F, int match_rounds, Arena &ar, hipStream_t st) {
+// member lists of F's aggregation (F.agg, F.nc): aggStart and aggCells in
+// ascending cell order
+static void agg_lists(Level &F, Arena &ar, hipStream_t st) {
+    Arena tmp;
+    const int32_t n = F.n, nc = F.nc;
+    const unsigned g = grid_n(n);
+    int32_t *cnt = tmp.get<int32_t>(nc);
+    int32_t *cursor = tmp.get<int32_t>(nc);
+    HIP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nc, st));
+    HIP_CHECK(hipMemsetAsync(cursor, 0, sizeof(int32_t) * nc, st));
+    k_agg_count<<<g, kBlock, 0, st>>>(n, F.agg, cnt);
+    F.aggStart = ar.get<int32_t>((size_t)nc + 1);
+    scan_counts_i32(cnt, F.aggStart, nc, tmp, st);
+    F.aggCells = ar.get<int32_t>(n);
+    k_agg_fill<<<g, kBlock, 0, st>>>(n, F.agg, F.aggStart, cursor, F.aggCells);
+    k_agg_sort<<<grid_n(nc), kBlock, 0, st>>>(nc, F.aggStart, F.aggCells);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// one pairwise matching pass over level F: F.agg (in ar) and F.nc; the member
+// lists go to lists_ar
+static int32_t agglomerate(ldu_t *h, Level &F, int match_rounds, Arena &ar, Arena &lists_ar,
+                           hipStream_t st) {
     const int32_t n = F.n;
     Arena tmp;
     int32_t *partner = tmp.get<int32_t>(n);
@@ -324,19 +346,39 @@ static int32_t agglomerate(ldu_t *h, Level &F, int match_rounds, Arena &ar, hipS
     F.nc = nc;
     F.agg = ar.get<int32_t>(n);
     k_match_assign<<<g, kBlock, 0, st>>>(n, partner, join, rank, F.agg);
-    int32_t *cnt = tmp.get<int32_t>(nc);
-    int32_t *cursor = tmp.get<int32_t>(nc);
-    HIP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nc, st));
-    HIP_CHECK(hipMemsetAsync(cursor, 0, sizeof(int32_t) * nc, st));
-    k_agg_count<<<g, kBlock, 0, st>>>(n, F.agg, cnt);
-    F.aggStart = ar.get<int32_t>((size_t)nc + 1);
-    scan_counts_i32(cnt, F.aggStart, nc, tmp, st);
-    F.aggCells = ar.get<int32_t>(n);
-    k_agg_fill<<<g, kBlock, 0, st>>>(n, F.agg, F.aggStart, cursor, F.aggCells);
-    k_agg_sort<<<grid_n(nc), kBlock, 0, st>>>(nc, F.aggStart, F.aggCells);
     HIP_CHECK(hipGetLastError());
-    HIP_CHECK(hipStreamSynchronize(st));
+    agg_lists(F, lists_ar, st);
     return nc;
+}
+
+__global__ void k_compose(int32_t n, const int32_t *__restrict__ outer, int32_t *agg) {
+    GRID_STRIDE(i, n) agg[i] = outer[agg[i]];
+}
+
+static void galerkin(ldu_t *h, Level &F, Level &C, Arena &ar, hipStream_t st);
+
+// aggregation of level F by `passes` pairwise matching passes: pass k matches
+// the aggregates of pass k-1 on their Galerkin matrix (a temporary, used only
+// for its coupling strengths) and the aggregate maps compose.  One pass is
+// plain pairwise agglomeration.
+static int32_t agglomerate_passes(ldu_t *h, Level &F, int match_rounds, int passes, Arena &ar,
+                                  hipStream_t st) {
+    if (passes <= 1) return agglomerate(h, F, match_rounds, ar, ar, st);
+    Arena tmp;
+    const int32_t nc = agglomerate(h, F, match_rounds, ar, tmp, st);
+    if (nc <= 1) {
+        agg_lists(F, ar, st);
+        return nc;
+    }
+    Level T;
+    galerkin(h, F, T, tmp, st);
+    build_level_sell(h, tmp, T, false, st);
+    const int32_t nc2 = agglomerate_passes(h, T, match_rounds, passes - 1, tmp, st);
+    k_compose<<<grid_n(F.n), kBlock, 0, st>>>(F.n, T.agg, F.agg);
+    HIP_CHECK(hipGetLastError());
+    F.nc = nc2;
+    agg_lists(F, ar, st);
+    return nc2;
 }
 
 static void galerkin(ldu_t *h, Level &F, Level &C, Arena &ar, hipStream_t st) {
@@ -380,7 +422,7 @@ void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
     while ((int)h->levels.size() < maxl) {
         const size_t l = h->levels.size() - 1;
         if (h->levels[l].n <= o.n_coarsest) break;
-        const int32_t nc = agglomerate(h, h->levels[l], o.match_rounds, ar, st);
+        const int32_t nc = agglomerate_passes(h, h->levels[l], o.match_rounds, o.passes, ar, st);
         if (100 * (int64_t)nc > 95 * (int64_t)h->levels[l].n) {
             h->levels[l].agg = nullptr;
             break;

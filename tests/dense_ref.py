@@ -85,3 +85,46 @@ def closed_form_1d(n, h, kind):
     else:
         raise ValueError(kind)
     return lam, V
+
+
+def pairwise_aggregation(n, owner, neighbour, upper, lower, diag):
+    """One pairwise agglomeration from its definition: greedy matching, then
+    each unmatched cell joins the aggregate of its strongest matched
+    neighbour (ties by tie key, then smaller index), else stays alone;
+    aggregates are numbered by their smallest seed cell.  Returns (agg, nc)."""
+    partner = greedy_matching(n, owner, neighbour, upper, lower, diag)
+    w = strength2(owner, neighbour, upper, lower, diag)
+    best = {}
+    for f in range(owner.size):
+        i, j = int(owner[f]), int(neighbour[f])
+        for a, b in ((i, j), (j, i)):
+            if partner[a] < 0 and partner[b] >= 0:
+                key = (w[f], tie_key(a, b), -b)
+                if a not in best or key > best[a][0]:
+                    best[a] = (key, b)
+    seeds = sorted(i for i in range(n)
+                   if (partner[i] >= 0 and i < partner[i]) or (partner[i] < 0 and i not in best))
+    rank = {s: k for k, s in enumerate(seeds)}
+    agg = np.empty(n, np.int64)
+    for i in range(n):
+        if partner[i] >= 0:
+            agg[i] = rank[min(i, int(partner[i]))]
+        elif i not in best:
+            agg[i] = rank[i]
+    for i, (_, j) in best.items():
+        agg[i] = rank[min(j, int(partner[j]))]
+    return agg, len(seeds)
+
+
+def galerkin_ldu(n, owner, neighbour, diag, upper, lower, agg, nc):
+    """P^T A P in LDU form, formed densely: coarse faces are the aggregate
+    pairs a < b joined by a fine face, in (a, b) order."""
+    A = dense(n, owner, neighbour, diag, upper, lower)
+    P = prolongation(agg, nc)
+    Ac = P.T @ A @ P
+    adj = np.zeros((n, n), bool)
+    adj[owner, neighbour] = True
+    adj[neighbour, owner] = True
+    pat = (P.T @ adj @ P) > 0
+    co, cn = np.nonzero(np.triu(pat, 1))
+    return co, cn, np.diag(Ac).copy(), Ac[co, cn], Ac[cn, co]

@@ -39,6 +39,7 @@ def test_default_options_and_null_arguments():
     assert o.rel_tol == 1e-8 and o.max_iter == 10000 and o.precond == 1
     g = ldu.gamg_opts()
     assert g.omega == 0.75 and g.n_pre == 2 and g.n_post == 2 and g.n_coarsest == 50
+    assert g.passes == 1
     h = ctypes.c_void_p()
     # argument checks happen before any device call
     assert ldu.lib().ldu_create(0, 0, None, None, None, None, None, None,

@@ -160,12 +160,14 @@ def _gamg_case(name):
     return CASES[name]
 
 
-@pytest.mark.parametrize("name", ["c2s", "c3s", "ragged", "c1", "nonsym"])
-def test_gamg_hierarchy_bit_exact(name):
+@pytest.mark.parametrize("name,passes", [("c2s", 1), ("c3s", 1), ("ragged", 1), ("c1", 1),
+                                         ("nonsym", 1), ("c2s", 2), ("c3s", 2), ("ragged", 3),
+                                         ("nonsym", 2)])
+def test_gamg_hierarchy_bit_exact(name, passes):
     c = _gamg_case(name)
     m = _lib().from_case(c)
-    m.gamg_setup()
-    g = O.Gamg(O.Ldu.from_case(c))
+    m.gamg_setup(passes=passes)
+    g = O.Gamg(O.Ldu.from_case(c), passes=passes)
     assert m.n_levels() == g.n_levels
     for l in range(g.n_levels):
         got = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in m.level(l).items()}
@@ -207,6 +209,29 @@ def test_gamg_solve_matches_oracle(name):
         xr = ref.x
     assert np.linalg.norm(xg - xr) <= 1e-10 * np.linalg.norm(xr)
     assert true_res(c, x.cpu().numpy()) <= 1e-8
+
+
+@pytest.mark.parametrize("passes", [2, 3])
+def test_aggressive_agglomeration_solves_match_oracle(passes):
+    c = _gamg_case("c5s")
+    A = O.Ldu.from_case(c)
+    g = O.Gamg(A, passes=passes)
+    m = _lib().from_case(c)
+    x, st = m.gamg(_t(c.rhs[0]), rel_tol=1e-8, passes=passes, history=300)
+    ref = g.solve(c.rhs[0], tol=1e-8)
+    assert st.n_levels == g.n_levels and st.converged and st.iterations == ref.iterations
+    assert hist_close(st.history, ref.history)
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    # CG preconditioned by the V-cycle of the same hierarchy
+    c3 = _gamg_case("c3p")
+    A3 = O.Ldu.from_case(c3)
+    m3 = _lib().from_case(c3)
+    m3.gamg_setup(passes=passes, n_pre=1, n_post=1)
+    x3, s3 = m3.pcg(_t(c3.rhs[0]), precond=2, rel_tol=1e-8)
+    r3 = O.Gamg(A3, passes=passes).pcg(c3.rhs[0], tol=1e-8, n_pre=1, n_post=1)
+    assert s3.converged and s3.iterations == r3.iterations
+    assert true_res(c3, x3.cpu().numpy()) <= 1e-8
+    assert np.linalg.norm(x3.cpu().numpy() - r3.x) <= 1e-9 * np.linalg.norm(r3.x)
 
 
 @pytest.mark.parametrize("solver", ["pcg", "gamg", "pcg_gamg"])

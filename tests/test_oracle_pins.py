@@ -14,7 +14,8 @@ from meshgen import (assemble_diag, box_case, box_faces, config_case,
                      random_order, relabel)
 from meshgen.boxes import LduCase, c3_spacing
 from tests.dense_ref import (closed_form_1d, dense, dense_case,
-                             greedy_matching, prolongation, strength2,
+                             galerkin_ldu, greedy_matching,
+                             pairwise_aggregation, prolongation, strength2,
                              tie_key)
 
 
@@ -590,3 +591,48 @@ def test_mixed_vcycle_pcg_refines_to_fp64_solution():
     assert r.status == O.OK and r.true_residual <= 1e-12
     assert np.linalg.norm(r.x - xd) <= 1e-10 * np.linalg.norm(xd)
     assert r.iterations <= 6
+
+
+# ---------------------------------------------------------------- aggressive agglomeration
+
+@pytest.mark.parametrize("passes", [2, 3])
+@pytest.mark.parametrize("idx", range(4))
+def test_aggressive_agglomeration_composes_pairwise_passes(idx, passes):
+    """passes > 1: pass k pairs the aggregates of pass k-1 on their Galerkin
+    matrix; built here from the dense definitions and composed."""
+    c = _match_cases()[idx]
+    g = O.Gamg(O.Ldu.from_case(c), n_coarsest=2, max_levels=2, match_rounds=100000,
+               passes=passes)
+    n, own, nb, d, up, lo = c.n_cells, c.owner, c.neighbour, c.diag, c.upper, c.lower
+    comp = np.arange(c.n_cells)
+    for _ in range(passes):
+        agg, nc = pairwise_aggregation(n, own, nb, up, lo, d)
+        comp = agg[comp]
+        if nc <= 1:
+            break
+        own, nb, d, up, lo = galerkin_ldu(n, own, nb, d, up, lo, agg, nc)
+        n = nc
+    assert np.array_equal(g.level(0).agg, comp)
+    # and the coarse matrix is P^T A P for the composed aggregation
+    C1 = g.level(1)
+    ro, rn, rd, ru, rl = galerkin_ldu(c.n_cells, c.owner, c.neighbour, c.diag, c.upper,
+                                      c.lower, comp, C1.n)
+    assert C1.n == comp.max() + 1
+    assert np.array_equal(C1.owner, ro) and np.array_equal(C1.neighbour, rn)
+    tol = 1e-14 * np.abs(c.diag).max()
+    assert np.allclose(C1.diag, rd, rtol=0, atol=tol)
+    assert np.allclose(C1.upper, ru, rtol=0, atol=tol)
+    assert np.allclose(C1.lower, rl, rtol=0, atol=tol)
+
+
+def test_aggressive_agglomeration_fewer_levels_and_converges():
+    c = box_case(12, 11, 10, coeff="lognormal", dirichlet_x0=1.0, seed=47)
+    A = O.Ldu.from_case(c)
+    levels = []
+    for passes in (1, 2, 3):
+        g = O.Gamg(A, passes=passes)
+        levels.append(g.n_levels)
+        r = g.solve(c.rhs[0], tol=1e-8, max_cycles=500)
+        assert r.status == O.OK
+        assert np.linalg.norm(c.rhs[0] - O.amul(A, r.x)) <= 1e-8 * np.linalg.norm(c.rhs[0])
+    assert levels[0] > levels[1] > levels[2]

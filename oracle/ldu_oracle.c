@@ -459,6 +459,9 @@ typedef struct {
 struct orc_gamg {
     int nlev;
     olevel lev[ORC_MAX_LEVELS];
+    int smoother;    /* ORC_SMOOTH_JACOBI or ORC_SMOOTH_GS2 */
+    int gs_inner;    /* two-stage Gauss-Seidel: inner Jacobi-Richardson steps */
+    int coarsest_pc; /* ORC_COARSE_DIAG or ORC_COARSE_DIC */
 };
 
 static uint64_t splitmix64_out(uint64_t z) {
@@ -711,6 +714,9 @@ orc_gamg *orc_gamg_build2(int32_t n, int64_t nf, const int32_t *own,
                           int n_coarsest, int max_levels, int match_rounds,
                           int passes) {
     orc_gamg *h = xcalloc(1, sizeof(orc_gamg));
+    h->smoother = ORC_SMOOTH_JACOBI;
+    h->gs_inner = 1;
+    h->coarsest_pc = ORC_COARSE_DIAG;
     if (max_levels > ORC_MAX_LEVELS) max_levels = ORC_MAX_LEVELS;
     if (max_levels < 1) max_levels = 1;
     olevel *L0 = &h->lev[0];
@@ -766,6 +772,16 @@ void orc_gamg_set_values(orc_gamg *h, const double *diag, const double *upper,
     set_singular(&h->lev[h->nlev - 1]);
 }
 
+int orc_gamg_set_cycle(orc_gamg *h, int smoother, int gs_inner, int coarsest_pc) {
+    if ((smoother != ORC_SMOOTH_JACOBI && smoother != ORC_SMOOTH_GS2) || gs_inner < 1 ||
+        (coarsest_pc != ORC_COARSE_DIAG && coarsest_pc != ORC_COARSE_DIC))
+        return ORC_ERR_ARG;
+    h->smoother = smoother;
+    h->gs_inner = gs_inner;
+    h->coarsest_pc = coarsest_pc;
+    return ORC_OK;
+}
+
 void orc_gamg_free(orc_gamg *h) {
     if (!h) return;
     for (int l = 0; l < h->nlev; ++l) free_level(&h->lev[l]);
@@ -809,11 +825,118 @@ static omat level_mat(const olevel *L, int transpose) {
                     transpose);
 }
 
-/* coarsest level: diagonal PCG from 0 to ||r|| <= 1e-10 ||rhs|| or
- * max(2n, 100) iterations; a singular level first projects its rhs to zero
- * mean (the constant null space of a pure zero-gradient operator) */
-static void coarsest_solve(const olevel *L, const double *r, double *e,
-                           int transpose) {
+/* ---- DIC (diagonal incomplete Cholesky) for the coarsest CG ------------ */
+/* The paper's alternative coarsest-level preconditioner (Sec. 4.3, smoother */
+/* and coarse-preconditioner table).  Textbook diagonal-modified ILU(0):      */
+/*   M = (Dt + L) Dt^-1 (Dt + U), with L, U the strictly lower / upper parts  */
+/*   of A and Dt chosen so that diag(M) = diag(A):                            */
+/*   Dt_i = A_ii - sum_{j<i} A_ij A_ji / Dt_j   (ascending j);                */
+/* for symmetric A this is the incomplete Cholesky of OpenFOAM's DIC.  A      */
+/* pivot that is not finite, or not of the sign of A_ii with magnitude above  */
+/* 1e-12 |A_ii|, marks the factorization unusable and the level falls back to */
+/* the diagonal preconditioner.                                               */
+/* Apply z = M^-1 r:                                                          */
+/*   forward  y_i = (r_i - sum_{j<i} A_ij y_j) / Dt_i,       i ascending      */
+/*   backward z_i = y_i - (sum_{j>i} A_ij z_j) / Dt_i,        i descending    */
+/* each row sum taken in ascending column order.                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n;
+    int64_t *lstart, *ustart; /* row i: lower entries [lstart[i], lstart[i+1]) */
+    int32_t *lcol, *ucol;
+    double *lval, *uval;
+    const double *diag;
+    double *dt;               /* Dt, the modified pivots */
+    int ok;
+} dic_fact;
+
+static void dic_build(const omat *m, dic_fact *F) {
+    const int32_t n = m->n;
+    const int64_t nf = m->nf;
+    F->n = n;
+    F->diag = m->diag;
+    F->lstart = xcalloc((size_t)n + 1, sizeof(int64_t));
+    F->ustart = xcalloc((size_t)n + 1, sizeof(int64_t));
+    F->lcol = xcalloc((size_t)nf + 1, sizeof(int32_t));
+    F->ucol = xcalloc((size_t)nf + 1, sizeof(int32_t));
+    F->lval = xcalloc((size_t)nf + 1, sizeof(double));
+    F->uval = xcalloc((size_t)nf + 1, sizeof(double));
+    F->dt = xcalloc((size_t)n + 1, sizeof(double));
+    /* row-wise lists: row nb[f] holds (own[f], lo[f]) in L; row own[f] holds
+     * (nb[f], up[f]) in U.  Faces are sorted by (owner, neighbour), so filling
+     * in face order leaves every row in ascending column order. */
+    for (int64_t f = 0; f < nf; ++f) {
+        F->lstart[m->nb[f] + 1]++;
+        F->ustart[m->own[f] + 1]++;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        F->lstart[i + 1] += F->lstart[i];
+        F->ustart[i + 1] += F->ustart[i];
+    }
+    int64_t *lc = xcalloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *uc = xcalloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t o = m->own[f], b = m->nb[f];
+        const int64_t pl = F->lstart[b] + lc[b]++;
+        F->lcol[pl] = o;
+        F->lval[pl] = m->lo[f];
+        const int64_t pu = F->ustart[o] + uc[o]++;
+        F->ucol[pu] = b;
+        F->uval[pu] = m->up[f];
+    }
+    free(lc); free(uc);
+    /* pivots: A_ji for a lower entry (i, j) is the upper entry of row j at
+     * column i, i.e. the same face */
+    F->ok = 1;
+    for (int32_t i = 0; i < n; ++i) {
+        double d = m->diag[i];
+        for (int64_t k = F->lstart[i]; k < F->lstart[i + 1]; ++k) {
+            const int32_t j = F->lcol[k];
+            double aji = 0.0;
+            for (int64_t q = F->ustart[j]; q < F->ustart[j + 1]; ++q)
+                if (F->ucol[q] == i) aji = F->uval[q];
+            d = d - (F->lval[k] * aji) / F->dt[j];
+        }
+        F->dt[i] = d;
+        if (!isfinite(d) || !(fabs(d) > 1e-12 * fabs(m->diag[i])) ||
+            (d > 0.0) != (m->diag[i] > 0.0))
+            F->ok = 0;
+    }
+}
+
+static void dic_free(dic_fact *F) {
+    free(F->lstart); free(F->ustart); free(F->lcol); free(F->ucol);
+    free(F->lval); free(F->uval); free(F->dt);
+}
+
+static void dic_apply(void *ctx, const double *r, double *z) {
+    const dic_fact *F = (const dic_fact *)ctx;
+    const int32_t n = F->n;
+    if (!F->ok) {
+        for (int32_t i = 0; i < n; ++i) z[i] = r[i] / F->diag[i];
+        return;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t k = F->lstart[i]; k < F->lstart[i + 1]; ++k)
+            s += F->lval[k] * z[F->lcol[k]];
+        z[i] = (r[i] - s) / F->dt[i];
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int64_t k = F->ustart[i]; k < F->ustart[i + 1]; ++k)
+            s += F->uval[k] * z[F->ucol[k]];
+        z[i] = z[i] - s / F->dt[i];
+    }
+}
+
+/* coarsest level: PCG (diagonal, or DIC when asked) from 0 to
+ * ||r|| <= 1e-10 ||rhs|| or max(2n, 100) iterations; a singular level first
+ * projects its rhs to zero mean (the constant null space of a pure
+ * zero-gradient operator) */
+static void coarsest_solve(const orc_gamg *h, const olevel *L, const double *r,
+                           double *e, int transpose) {
     const int32_t n = L->n;
     omat m = level_mat(L, transpose);
     double *rhs = xcalloc(n, sizeof(double));
@@ -834,7 +957,15 @@ static void coarsest_solve(const olevel *L, const double *r, double *e,
         w.q = xcalloc(n, sizeof(double));
         int total = 0;
         int max_it = 2 * n > 100 ? 2 * n : 100;
-        cg_run(&m, 1, e, &w, bn, COARSEST_TOL, max_it, &total, NULL);
+        if (h->coarsest_pc == ORC_COARSE_DIC) {
+            dic_fact F;
+            dic_build(&m, &F);
+            cg_run_pc(&m, 1, dic_apply, &F, e, &w, bn, COARSEST_TOL, max_it, &total,
+                      NULL);
+            dic_free(&F);
+        } else {
+            cg_run(&m, 1, e, &w, bn, COARSEST_TOL, max_it, &total, NULL);
+        }
         free(w.z); free(w.p); free(w.q);
     }
     free(rhs);
@@ -854,25 +985,69 @@ static void jacobi_sweep(const omat *m, const double *r, double *e,
     memcpy(e, y, (size_t)m->n * sizeof(double));
 }
 
+/* y = L x (strictly lower part: row nb[f], column own[f]) or y = U x
+ * (strictly upper: row own[f], column nb[f]); each row sums its terms in
+ * ascending column order, which is face order for a face list sorted by
+ * (owner, neighbour) */
+static void tri_mul(const omat *m, int upper, const double *x, double *y) {
+    for (int32_t i = 0; i < m->n; ++i) y[i] = 0.0;
+    for (int64_t f = 0; f < m->nf; ++f) {
+        if (upper) y[m->own[f]] += m->up[f] * x[m->nb[f]];
+        else y[m->nb[f]] += m->lo[f] * x[m->own[f]];
+    }
+}
+
+/* ---- two-stage Gauss-Seidel smoother ------------------------------------ */
+/* The paper's second GPU smoother (Sec. 4.3), after Berger-Vergiat et al.    */
+/* (2021): a Gauss-Seidel sweep e += (D + L)^-1 (r - A e) whose triangular    */
+/* solve is replaced by `inner` Jacobi-Richardson steps                       */
+/*   t = r - A e;  g = D^-1 t;  repeat inner times: g = D^-1 (t - L g);       */
+/*   e = e + g.                                                               */
+/* Forward sweeps (L) pre-smooth, backward sweeps (U, i.e. (D + U)^-1) post-  */
+/* smooth, so a V-cycle with n_pre = n_post is symmetric for symmetric A.     */
+/* A sweep from e = 0 takes t = r and sets e = g.  No damping.                */
+/* ------------------------------------------------------------------------ */
+static void gs2_sweep(const omat *m, const double *r, double *e, int from_zero,
+                      int backward, int inner, double *t, double *g,
+                      double *y) {
+    const int32_t n = m->n;
+    if (from_zero) memcpy(t, r, (size_t)n * sizeof(double));
+    else residual(m, r, e, t);
+    for (int32_t i = 0; i < n; ++i) g[i] = t[i] / m->diag[i];
+    for (int k = 0; k < inner; ++k) {
+        tri_mul(m, backward, g, y);
+        for (int32_t i = 0; i < n; ++i) g[i] = (t[i] - y[i]) / m->diag[i];
+    }
+    for (int32_t i = 0; i < n; ++i) e[i] = from_zero ? g[i] : e[i] + g[i];
+}
+
 static void vcycle(const orc_gamg *h, int l, const double *r, double *e,
                    const vparams *vp) {
     const olevel *L = &h->lev[l];
     if (l == h->nlev - 1) {
-        coarsest_solve(L, r, e, vp->transpose);
+        coarsest_solve(h, L, r, e, vp->transpose);
         return;
     }
     const int32_t n = L->n;
     const olevel *C = &h->lev[l + 1];
     omat m = level_mat(L, vp->transpose);
+    const int gs = h->smoother == ORC_SMOOTH_GS2;
     double *y = xcalloc(n, sizeof(double));
     double *t = xcalloc(n, sizeof(double));
     double *c = xcalloc(n, sizeof(double));
+    double *g = xcalloc(n, sizeof(double));
     double *rc = xcalloc(C->n, sizeof(double));
     double *ec = xcalloc(C->n, sizeof(double));
-    /* pre-smoothing from e = 0: the first sweep is omega*r/diag */
-    for (int32_t i = 0; i < n; ++i)
-        e[i] = vp->n_pre > 0 ? vp->omega * r[i] / m.diag[i] : 0.0;
-    for (int s = 1; s < vp->n_pre; ++s) jacobi_sweep(&m, r, e, y, vp->omega);
+    /* pre-smoothing from e = 0 (Jacobi: the first sweep is omega*r/diag) */
+    if (gs) {
+        for (int32_t i = 0; i < n; ++i) e[i] = 0.0;
+        for (int s = 0; s < vp->n_pre; ++s)
+            gs2_sweep(&m, r, e, s == 0, 0, h->gs_inner, t, g, y);
+    } else {
+        for (int32_t i = 0; i < n; ++i)
+            e[i] = vp->n_pre > 0 ? vp->omega * r[i] / m.diag[i] : 0.0;
+        for (int s = 1; s < vp->n_pre; ++s) jacobi_sweep(&m, r, e, y, vp->omega);
+    }
     /* residual after smoothing, restricted by summation (restrictField) */
     residual(&m, r, e, t);
     for (int32_t i = 0; i < n; ++i) rc[L->agg[i]] += t[i];
@@ -887,8 +1062,38 @@ static void vcycle(const orc_gamg *h, int l, const double *r, double *e,
         if (isfinite(cac) && fabs(cac) > 1e-300) s = ct / cac;
     }
     for (int32_t i = 0; i < n; ++i) e[i] = e[i] + s * c[i];
-    for (int k = 0; k < vp->n_post; ++k) jacobi_sweep(&m, r, e, y, vp->omega);
-    free(y); free(t); free(c); free(rc); free(ec);
+    for (int k = 0; k < vp->n_post; ++k) {
+        if (gs) gs2_sweep(&m, r, e, 0, 1, h->gs_inner, t, g, y);
+        else jacobi_sweep(&m, r, e, y, vp->omega);
+    }
+    free(y); free(t); free(c); free(g); free(rc); free(ec);
+}
+
+/* single steps exposed for the pins: one two-stage Gauss-Seidel sweep, and
+ * the DIC pivots / preconditioner application on one matrix */
+void orc_gs2_sweep(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+                   const double *diag, const double *upper, const double *lower,
+                   const double *r, double *e, int from_zero, int backward,
+                   int inner) {
+    omat m = make_mat(n, nf, own, nb, diag, upper, lower, 0);
+    double *t = xcalloc((size_t)n + 1, sizeof(double));
+    double *g = xcalloc((size_t)n + 1, sizeof(double));
+    double *y = xcalloc((size_t)n + 1, sizeof(double));
+    gs2_sweep(&m, r, e, from_zero, backward, inner, t, g, y);
+    free(t); free(g); free(y);
+}
+
+int orc_dic(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+            const double *diag, const double *upper, const double *lower,
+            double *dt, const double *r, double *z) {
+    omat m = make_mat(n, nf, own, nb, diag, upper, lower, 0);
+    dic_fact F;
+    dic_build(&m, &F);
+    if (dt) memcpy(dt, F.dt, (size_t)n * sizeof(double));
+    if (r && z) dic_apply(&F, r, z);
+    const int ok = F.ok;
+    dic_free(&F);
+    return ok;
 }
 
 int orc_gamg_vcycle(const orc_gamg *h, const double *r, double *e, int n_pre,
@@ -980,6 +1185,32 @@ static void jacobi_sweep32(const fmat *m, const float *r, float *e, float *y,
     memcpy(e, y, (size_t)m->n * sizeof(float));
 }
 
+static void tri_mul32(const fmat *m, int upper, const float *x, float *y) {
+    for (int32_t i = 0; i < m->n; ++i) y[i] = 0.0f;
+    for (int64_t f = 0; f < m->nf; ++f) {
+        if (upper) y[m->own[f]] += m->up[f] * x[m->nb[f]];
+        else y[m->nb[f]] += m->lo[f] * x[m->own[f]];
+    }
+}
+
+/* the two-stage Gauss-Seidel sweep in FP32 (same steps as gs2_sweep) */
+static void gs2_sweep32(const fmat *m, const float *r, float *e, int from_zero,
+                        int backward, int inner, float *t, float *g, float *y) {
+    const int32_t n = m->n;
+    if (from_zero) {
+        memcpy(t, r, (size_t)n * sizeof(float));
+    } else {
+        fmat_mul(m, e, t);
+        for (int32_t i = 0; i < n; ++i) t[i] = r[i] - t[i];
+    }
+    for (int32_t i = 0; i < n; ++i) g[i] = t[i] / m->diag[i];
+    for (int k = 0; k < inner; ++k) {
+        tri_mul32(m, backward, g, y);
+        for (int32_t i = 0; i < n; ++i) g[i] = (t[i] - y[i]) / m->diag[i];
+    }
+    for (int32_t i = 0; i < n; ++i) e[i] = from_zero ? g[i] : e[i] + g[i];
+}
+
 static void vcycle32(const orc_gamg *h, int l, const float *r, float *e,
                      const vparams *vp) {
     const olevel *L = &h->lev[l];
@@ -988,7 +1219,7 @@ static void vcycle32(const orc_gamg *h, int l, const float *r, float *e,
         double *rd = xcalloc(n, sizeof(double));
         double *ed = xcalloc(n, sizeof(double));
         for (int32_t i = 0; i < n; ++i) rd[i] = (double)r[i];
-        coarsest_solve(L, rd, ed, vp->transpose);
+        coarsest_solve(h, L, rd, ed, vp->transpose);
         for (int32_t i = 0; i < n; ++i) e[i] = (float)ed[i];
         free(rd); free(ed);
         return;
@@ -997,14 +1228,22 @@ static void vcycle32(const orc_gamg *h, int l, const float *r, float *e,
     fmat m;
     level_fmat(L, vp->transpose, &m);
     const float omega = (float)vp->omega;
+    const int gs = h->smoother == ORC_SMOOTH_GS2;
     float *y = xcalloc(n, sizeof(float));
     float *t = xcalloc(n, sizeof(float));
     float *c = xcalloc(n, sizeof(float));
+    float *g = xcalloc(n, sizeof(float));
     float *rc = xcalloc(C->n, sizeof(float));
     float *ec = xcalloc(C->n, sizeof(float));
-    for (int32_t i = 0; i < n; ++i)
-        e[i] = vp->n_pre > 0 ? omega * r[i] / m.diag[i] : 0.0f;
-    for (int s = 1; s < vp->n_pre; ++s) jacobi_sweep32(&m, r, e, y, omega);
+    if (gs) {
+        for (int32_t i = 0; i < n; ++i) e[i] = 0.0f;
+        for (int s = 0; s < vp->n_pre; ++s)
+            gs2_sweep32(&m, r, e, s == 0, 0, h->gs_inner, t, g, y);
+    } else {
+        for (int32_t i = 0; i < n; ++i)
+            e[i] = vp->n_pre > 0 ? omega * r[i] / m.diag[i] : 0.0f;
+        for (int s = 1; s < vp->n_pre; ++s) jacobi_sweep32(&m, r, e, y, omega);
+    }
     fmat_mul(&m, e, t);
     for (int32_t i = 0; i < n; ++i) t[i] = r[i] - t[i];
     for (int32_t i = 0; i < n; ++i) rc[L->agg[i]] += t[i];
@@ -1018,8 +1257,11 @@ static void vcycle32(const orc_gamg *h, int l, const float *r, float *e,
         if (isfinite(cac) && fabs(cac) > 1e-300) sf = (float)(ct / cac);
     }
     for (int32_t i = 0; i < n; ++i) e[i] = e[i] + sf * c[i];
-    for (int k = 0; k < vp->n_post; ++k) jacobi_sweep32(&m, r, e, y, omega);
-    free(y); free(t); free(c); free(rc); free(ec);
+    for (int k = 0; k < vp->n_post; ++k) {
+        if (gs) gs2_sweep32(&m, r, e, 0, 1, h->gs_inner, t, g, y);
+        else jacobi_sweep32(&m, r, e, y, omega);
+    }
+    free(y); free(t); free(c); free(g); free(rc); free(ec);
 }
 
 typedef struct {

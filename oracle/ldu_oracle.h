@@ -77,6 +77,22 @@ orc_gamg *orc_gamg_build2(int32_t n, int64_t nf, const int32_t *own,
                           int n_coarsest, int max_levels, int match_rounds,
                           int passes);
 void orc_gamg_free(orc_gamg *h);
+/* cycle variants: smoother (Jacobi, or two-stage Gauss-Seidel with gs_inner
+ * inner steps) and the coarsest-level CG preconditioner (diagonal or DIC) */
+enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_GS2 = 1 };
+enum { ORC_COARSE_DIAG = 0, ORC_COARSE_DIC = 1 };
+int orc_gamg_set_cycle(orc_gamg *h, int smoother, int gs_inner, int coarsest_pc);
+/* one two-stage Gauss-Seidel sweep on A e = r (e in/out; from_zero ignores
+ * e's input); backward uses the upper triangle */
+void orc_gs2_sweep(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+                   const double *diag, const double *upper, const double *lower,
+                   const double *r, double *e, int from_zero, int backward,
+                   int inner);
+/* DIC pivots Dt (dt may be NULL) and z = M^-1 r (r, z may be NULL); returns 1
+ * when every pivot is usable, 0 when the diagonal fallback applies */
+int orc_dic(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+            const double *diag, const double *upper, const double *lower,
+            double *dt, const double *r, double *z);
 /* new level-0 coefficients; aggregation kept, coarse matrices recomputed */
 void orc_gamg_set_values(orc_gamg *h, const double *diag, const double *upper,
                          const double *lower);

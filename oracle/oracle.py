@@ -78,6 +78,10 @@ def lib():
     L.orc_gamg_build2.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p,
                                   C.c_int, C.c_int, C.c_int, C.c_int]
     L.orc_gamg_free.argtypes = [vp]
+    L.orc_gamg_set_cycle.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    L.orc_gs2_sweep.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p,
+                                C.c_int, C.c_int, C.c_int]
+    L.orc_dic.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64o, _f64o, _f64o]
     L.orc_gamg_set_values.argtypes = [vp, _f64p, _f64p, _f64p]
     L.orc_gamg_nlevels.argtypes = [vp]
     L.orc_gamg_level_size.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(i64)]
@@ -208,12 +212,22 @@ class Level:
 class Gamg:
     """Oracle GAMG hierarchy (built once; values and structure fixed)."""
 
+    SMOOTHERS = {"jacobi": 0, "gs2": 1}
+    COARSEST = {"diag": 0, "dic": 1}
+
     def __init__(self, A: Ldu, n_coarsest=50, max_levels=50, match_rounds=16,
-                 passes=1):
+                 passes=1, smoother="jacobi", gs_inner=1, coarsest="diag"):
+        """smoother: "jacobi" (damped Jacobi / Richardson) or "gs2" (two-stage
+        Gauss-Seidel with gs_inner inner steps); coarsest: the coarsest-level
+        CG preconditioner, "diag" or "dic"."""
         self.A = A
         self._h = lib().orc_gamg_build2(*A.args(), int(n_coarsest),
                                         int(max_levels), int(match_rounds),
                                         int(passes))
+        rc = lib().orc_gamg_set_cycle(self._h, self.SMOOTHERS[smoother], int(gs_inner),
+                                      self.COARSEST[coarsest])
+        if rc != OK:
+            raise ValueError("invalid cycle options")
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
@@ -321,3 +335,19 @@ def coeff_grad(A: Ldu, lam, x):
     lib().orc_coeff_grad(A.n, A.nf, A.own, A.nb, _c(lam, np.float64),
                          _c(x, np.float64), gd, gu, gl)
     return gd, gu, gl
+
+
+def gs2_sweep(A: Ldu, r, e=None, backward=False, inner=1):
+    """One two-stage Gauss-Seidel sweep on A e = r (from e = 0 when e is None)."""
+    out = np.zeros(A.n) if e is None else _c(e, np.float64).copy()
+    lib().orc_gs2_sweep(*A.args(), _c(r, np.float64), out, int(e is None),
+                        int(bool(backward)), int(inner))
+    return out
+
+
+def dic(A: Ldu, r=None):
+    """DIC pivots Dt, usability flag, and z = M^-1 r when r is given."""
+    dt = np.empty(A.n)
+    z = None if r is None else np.empty(A.n)
+    ok = lib().orc_dic(*A.args(), dt, None if r is None else _c(r, np.float64), z)
+    return dt, bool(ok), z

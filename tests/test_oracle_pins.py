@@ -636,3 +636,142 @@ def test_aggressive_agglomeration_fewer_levels_and_converges():
         assert r.status == O.OK
         assert np.linalg.norm(c.rhs[0] - O.amul(A, r.x)) <= 1e-8 * np.linalg.norm(c.rhs[0])
     assert levels[0] > levels[1] > levels[2]
+
+
+# ---------------------------------------------------------------- two-stage Gauss-Seidel, DIC
+
+def _tri_parts(c):
+    D = dense_case(c)
+    return D, np.diag(np.diag(D)), np.tril(D, -1), np.triu(D, 1)
+
+
+def test_gs2_inner_steps_converge_to_the_triangular_solve():
+    """D^-1 L is nilpotent, so the inner Jacobi-Richardson steps give
+    (D + L)^-1 t exactly once their number reaches the longest chain of the
+    lower-triangular graph (n - 1 on a 1D chain), and not before."""
+    from scipy.linalg import solve_triangular
+    c = box_case(9, 1, 1, coeff="lognormal", dirichlet_x0=1.0, seed=51)
+    A = O.Ldu.from_case(c)
+    D, Dg, L, U = _tri_parts(c)
+    r = np.random.default_rng(52).standard_normal(c.n_cells)
+    fwd = solve_triangular(Dg + L, r, lower=True)
+    bwd = solve_triangular(Dg + U, r, lower=False)
+    n = c.n_cells
+    for backward, ref in ((False, fwd), (True, bwd)):
+        exact = O.gs2_sweep(A, r, backward=backward, inner=n - 1)
+        assert np.linalg.norm(exact - ref) <= 1e-13 * np.linalg.norm(ref)
+        short = O.gs2_sweep(A, r, backward=backward, inner=n - 2)
+        assert np.linalg.norm(short - ref) > 1e-6 * np.linalg.norm(ref)
+    # a sweep from a nonzero e corrects by the triangular solve of r - A e
+    e0 = np.random.default_rng(53).standard_normal(n)
+    got = O.gs2_sweep(A, r, e0, inner=n - 1)
+    want = e0 + solve_triangular(Dg + L, r - D @ e0, lower=True)
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+
+
+def test_gs2_unstructured_limit_and_one_step_bound():
+    from scipy.linalg import solve_triangular
+    c = _perm_case(box_case(5, 4, 3, coeff="lognormal", nonsym=0.4, dirichlet_x0=1.0,
+                            seed=54), 55)
+    A = O.Ldu.from_case(c)
+    D, Dg, L, U = _tri_parts(c)
+    r = np.random.default_rng(56).standard_normal(c.n_cells)
+    ref = solve_triangular(Dg + L, r, lower=True)
+    got = O.gs2_sweep(A, r, inner=c.n_cells)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    # one inner step: the error of the triangular solve is (D^-1 L)^2 applied
+    # to the exact answer, so it is bounded by ||D^-1 L||^2 ||ref||
+    one = O.gs2_sweep(A, r, inner=1)
+    K = np.linalg.norm(np.linalg.solve(Dg, L), 2)
+    assert np.linalg.norm(one - ref) <= K ** 2 * np.linalg.norm(ref) * (1 + 1e-12)
+
+
+def test_vcycle_gs2_two_level_dense_formula():
+    """With exact triangular solves the two-stage smoother is Gauss-Seidel:
+    forward sweeps before the coarse correction, backward sweeps after."""
+    from scipy.linalg import solve_triangular
+    c = box_case(5, 4, 3, coeff="lognormal", dirichlet_x0=1.0, seed=3)
+    n = c.n_cells
+    g = O.Gamg(O.Ldu.from_case(c), n_coarsest=40, max_levels=2, smoother="gs2",
+               gs_inner=n)
+    assert g.n_levels == 2
+    D, Dg, L, U = _tri_parts(c)
+    P = prolongation(g.level(0).agg, g.level(1).n)
+    Ac = P.T @ D @ P
+    r = np.random.default_rng(57).standard_normal(n)
+    e = solve_triangular(Dg + L, r, lower=True)
+    e = e + solve_triangular(Dg + L, r - D @ e, lower=True)
+    t = r - D @ e
+    cc = P @ np.linalg.solve(Ac, P.T @ t)
+    e = e + ((cc @ t) / (cc @ (D @ cc))) * cc
+    for _ in range(2):
+        e = e + solve_triangular(Dg + U, r - D @ e, lower=False)
+    got = g.vcycle(r, n_pre=2, n_post=2, scale=True)
+    assert np.linalg.norm(got - e) <= 1e-8 * np.linalg.norm(e)
+
+
+@pytest.mark.parametrize("inner", [1, 2])
+def test_vcycle_gs2_is_symmetric_without_scaling(inner):
+    c = box_case(7, 6, 5, coeff="lognormal", dirichlet_x0=1.0, seed=9)
+    g = O.Gamg(O.Ldu.from_case(c), n_coarsest=10, smoother="gs2", gs_inner=inner)
+    rng = np.random.default_rng(58)
+    u, v = rng.standard_normal((2, c.n_cells))
+    Vu = g.vcycle(u, scale=False)
+    Vv = g.vcycle(v, scale=False)
+    assert abs(u @ Vv - v @ Vu) <= 1e-8 * np.linalg.norm(u) * np.linalg.norm(Vv)
+    # but not with forward sweeps on both sides: the pairing matters
+    g2 = O.Gamg(O.Ldu.from_case(c), n_coarsest=10, smoother="gs2", gs_inner=inner)
+    Vu1 = g2.vcycle(u, n_pre=1, n_post=0, scale=False)
+    Vv1 = g2.vcycle(v, n_pre=1, n_post=0, scale=False)
+    assert abs(u @ Vv1 - v @ Vu1) > 1e-6 * np.linalg.norm(u) * np.linalg.norm(Vv1)
+
+
+@pytest.mark.parametrize("nonsym", [0.0, 0.5])
+def test_dic_reproduces_the_diagonal_and_inverts_its_factors(nonsym):
+    c = _perm_case(box_case(5, 4, 3, coeff="lognormal", nonsym=nonsym, dirichlet_x0=1.0,
+                            seed=59), 60)
+    A = O.Ldu.from_case(c)
+    D, Dg, L, U = _tri_parts(c)
+    r = np.random.default_rng(61).standard_normal(c.n_cells)
+    dt, ok, z = O.dic(A, r)
+    assert ok
+    Dt = np.diag(dt)
+    M = (Dt + L) @ np.diag(1.0 / dt) @ (Dt + U)
+    # the modified pivots make diag(M) = diag(A); on a box mesh (no
+    # triangles in the graph) M - A also vanishes on A's off-diagonal pattern
+    assert np.allclose(np.diag(M), np.diag(D), rtol=1e-13, atol=0)
+    pat = (D != 0) & ~np.eye(c.n_cells, dtype=bool)
+    assert np.max(np.abs((M - D)[pat])) <= 1e-13 * np.abs(D).max()
+    assert np.linalg.norm(M @ z - r) <= 1e-13 * np.linalg.norm(r) * np.linalg.cond(M)
+
+
+def test_dic_is_exact_on_a_chain_and_falls_back_when_singular():
+    c = box_case(10, 1, 1, coeff="lognormal", dirichlet_x0=1.0, seed=62)
+    A = O.Ldu.from_case(c)
+    r = np.random.default_rng(63).standard_normal(c.n_cells)
+    _, ok, z = O.dic(A, r)
+    # a tridiagonal matrix has no fill: M = A
+    assert ok and np.allclose(z, np.linalg.solve(dense_case(c), r), rtol=1e-12, atol=0)
+    # pure zero-gradient chain: the last exact pivot is 0, so the level uses
+    # the diagonal preconditioner
+    cs = box_case(10, 1, 1, coeff="lognormal", seed=64)
+    As = O.Ldu.from_case(cs)
+    _, oks, zs = O.dic(As, r)
+    assert not oks and np.array_equal(zs, r / cs.diag)
+
+
+@pytest.mark.parametrize("smoother,coarsest", [("gs2", "diag"), ("jacobi", "dic"),
+                                               ("gs2", "dic")])
+def test_gamg_variants_converge_to_dense_solution(smoother, coarsest):
+    c = _perm_case(box_case(8, 7, 6, coeff="lognormal", dirichlet_x0=1.0, seed=12), 13)
+    A = O.Ldu.from_case(c)
+    xd = np.linalg.solve(dense_case(c), c.rhs[0])
+    g = O.Gamg(A, n_coarsest=60, smoother=smoother, coarsest=coarsest)
+    r = g.solve(c.rhs[0], tol=1e-12, max_cycles=500)
+    assert r.status == O.OK and np.linalg.norm(r.x - xd) <= 1e-10 * np.linalg.norm(xd)
+    p = g.pcg(c.rhs[0], tol=1e-12)
+    assert p.status == O.OK and np.linalg.norm(p.x - xd) <= 1e-10 * np.linalg.norm(xd)
+    # a one-level hierarchy is the coarsest solve itself: 1e-10 relative
+    g1 = O.Gamg(A, n_coarsest=10 ** 6, coarsest=coarsest)
+    e = g1.vcycle(c.rhs[0])
+    assert np.linalg.norm(c.rhs[0] - O.amul(A, e)) <= 1e-10 * np.linalg.norm(c.rhs[0])

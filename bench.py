@@ -229,7 +229,41 @@ def main():
     log(f"[bench] adjoint: {t_adj:.4f} s, {sa.iterations} iterations; coeff_grad "
         f"{t_grad * 1e6:.0f} us")
 
+    # variants of the same solve (each one warm-up, then the mean of two):
+    # aggressive agglomeration (two and three matching passes per level), the
+    # two-stage Gauss-Seidel smoother, the DIC coarsest preconditioner
+    variants = {}
+    for name, kw in (("aggressive_2pass", dict(passes=2)),
+                     ("aggressive_3pass", dict(passes=3)),
+                     ("gs2_smoother", dict(smoother="gs2")),
+                     ("dic_coarsest", dict(coarsest="dic")),
+                     ("aggressive_2pass_gs2", dict(passes=2, smoother="gs2"))):
+        t0 = time.perf_counter()
+        m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, **kw)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        rec = {"setup_s": ts, "levels": m.n_levels()}
+        for prec in ("fp64", "mixed"):
+            vo = dict(opts, precision=prec)
+            m.pcg(b, **vo)
+            vt = []
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xv, sv = m.pcg(b, **vo)
+                torch.cuda.synchronize()
+                vt.append(time.perf_counter() - t0)
+            vres = m.residual(b, xv)
+            assert sv.converged and vres <= 1e-8, (name, prec, sv, vres)
+            rec[prec] = {"s": float(np.mean(vt)), "iterations": sv.iterations,
+                         "refinements": sv.refinements, "true_residual": vres}
+        variants[name] = rec
+        log(f"[bench] variant {name}: {rec['levels']} levels, fp64 {rec['fp64']['s']:.4f} s "
+            f"({rec['fp64']['iterations']} it), mixed {rec['mixed']['s']:.4f} s")
+    m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
+
     extra = {
+        "variants": variants,
         "adjoint": {"solve_s": t_adj, "iterations": sa.iterations,
                     "coeff_grad_us": t_grad * 1e6,
                     "coeff_grad_GBps": amul_bytes(case.n_cells, case.n_faces) / t_grad / 1e9},

@@ -56,6 +56,10 @@ enum {
 };
 
 enum { LDU_FP64 = 0, LDU_MIXED = 1 };
+/* GAMG smoothers and coarsest-level CG preconditioners (Sec. 4.3 compares
+ * both smoothers and both coarsest preconditioners) */
+enum { LDU_SMOOTH_JACOBI = 0, LDU_SMOOTH_GS2 = 1 };
+enum { LDU_COARSE_DIAG = 0, LDU_COARSE_DIC = 1 };
 
 typedef struct ldu_t *ldu_handle;
 
@@ -82,7 +86,8 @@ typedef struct {
 /* Options of gamg_setup / gamg_solve.  Defaults (ldu_gamg_default_opts):
  * rel_tol 1e-8, max_cycles 200, n_coarsest 50, n_pre 2, n_post 2,
  * max_levels 50, scale_correction 1, match_rounds 16, precision LDU_FP64,
- * max_refine 200, omega 0.75, passes 1. */
+ * max_refine 200, omega 0.75, passes 1, smoother LDU_SMOOTH_JACOBI,
+ * gs_inner 1, coarsest LDU_COARSE_DIAG. */
 typedef struct {
     double rel_tol;
     double abs_tol;        /* unused, reserved: must be 0 */
@@ -101,6 +106,19 @@ typedef struct {
                             * 2^passes cells and the hierarchy has fewer levels
                             * (aggressive agglomeration, the remedy the paper
                             * points to for GAMG's many tiny levels, Sec. 4.4) */
+    int smoother;          /* LDU_SMOOTH_JACOBI: damped Jacobi (Richardson) with
+                            * omega; LDU_SMOOTH_GS2: two-stage Gauss-Seidel
+                            * (Berger-Vergiat et al. 2021): each sweep corrects
+                            * e by gs_inner Jacobi-Richardson steps that
+                            * approximate (D + L)^-1 (r - A e); forward sweeps
+                            * before the coarse correction, backward (D + U)
+                            * after it; omega unused */
+    int gs_inner;          /* inner steps per two-stage sweep, 1..8 */
+    int coarsest;          /* coarsest-level CG preconditioner: LDU_COARSE_DIAG,
+                            * or LDU_COARSE_DIC (diagonal incomplete Cholesky,
+                            * M = (Dt + L) Dt^-1 (Dt + U) with diag(M) = diag(A);
+                            * falls back to the diagonal when a pivot is not
+                            * usable) */
 } ldu_gamg_opts;
 
 typedef struct {

@@ -83,6 +83,9 @@ void check_gamg_opts(const ldu_gamg_opts &o) {
         o.n_pre < 0 || o.n_post < 0 || o.max_levels < 1 || o.max_levels > kMaxLevels ||
         o.match_rounds < 0 || (o.precision != LDU_FP64 && o.precision != LDU_MIXED) ||
         o.max_refine < 0 || !(o.omega > 0.0) || o.passes < 1 || o.passes > 3 ||
+        (o.smoother != LDU_SMOOTH_JACOBI && o.smoother != LDU_SMOOTH_GS2) ||
+        o.gs_inner < 1 || o.gs_inner > 8 ||
+        (o.coarsest != LDU_COARSE_DIAG && o.coarsest != LDU_COARSE_DIC) ||
         (o.scale_correction != 0 && o.scale_correction != 1))
         throw Error(LDU_ERR_ARG, "invalid ldu_gamg_opts");
 }
@@ -132,6 +135,9 @@ void ldu_gamg_default_opts(ldu_gamg_opts *o) {
     o->max_refine = 200;
     o->omega = 0.75;
     o->passes = 1;
+    o->smoother = LDU_SMOOTH_JACOBI;
+    o->gs_inner = 1;
+    o->coarsest = LDU_COARSE_DIAG;
 }
 
 const char *ldu_last_error(void) { return g_last_error.c_str(); }

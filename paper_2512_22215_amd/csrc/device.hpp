@@ -173,6 +173,46 @@ __device__ __forceinline__ T sell_row(const SellView<T> &A, int64_t s, int lane,
     return acc;
 }
 
+// strictly lower (UPPER false: columns < i) or strictly upper (columns > i)
+// part of row i applied to x, summed from zero in column order; padding
+// entries (column == i) drop out with the mask
+template <bool CMP, bool UPPER, typename T, class XA>
+__device__ __forceinline__ T sell_tri(const SellView<T> &A, int64_t s, int lane, int32_t i,
+                                      const XA &xa) {
+    const int64_t b0 = A.sptr[s];
+    T acc = T(0);
+    const int32_t *cp = A.col + b0 + lane;
+    const T *vp = A.val + b0 + lane;
+    int w;
+    const int32_t *ot = nullptr;
+    if constexpr (CMP) {
+        w = A.pdeg[s * kWave + lane];
+        ot = A.otab + A.tptr[s];
+    } else {
+        w = (int)((A.sptr[s + 1] - b0) >> 6);
+    }
+    for (int k = 0; k < w; k += 8) {
+        int32_t c[8];
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (k + u < w) {
+                const int64_t o = CMP ? (int64_t)ot[k + u] : (int64_t)(k + u) * kWave;
+                c[u] = __builtin_nontemporal_load(cp + o);
+                v[u] = __builtin_nontemporal_load(vp + o);
+            }
+        }
+        T xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k + u < w) xv[u] = xa(c[u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k + u < w && (UPPER ? c[u] > i : c[u] < i)) acc = acc + v[u] * xv[u];
+    }
+    return acc;
+}
+
 // either layout, decided at run time (small levels and setup kernels)
 template <typename T, class XA>
 __device__ __forceinline__ T sell_row_any(const SellView<T> &A, int64_t s, int lane, int32_t i,

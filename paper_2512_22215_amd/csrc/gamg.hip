@@ -433,7 +433,9 @@ void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
         h->levels.push_back(C);
     }
     for (auto &L : h->levels) alloc_work(L, ar);
-    h->coarse_work = ar.get<double>(4 * (size_t)h->levels.back().n);
+    h->coarse_work = ar.get<double>(5 * (size_t)h->levels.back().n);
+    h->dic_dt = ar.get<double>(h->levels.back().n);
+    h->dic_ready = false;
 
     if (h->L0.A.val32) ensure_f32_levels(h, st);
     detect_singular(h, h->levels.back(), st);
@@ -452,6 +454,44 @@ void gamg_refresh_values(ldu_t *h, hipStream_t st) {
         refresh_f32(C, st);
     }
     detect_singular(h, h->levels.back(), st);
+    h->dic_ready = false;
+}
+
+// DIC pivots of the coarsest level (diagonal incomplete Cholesky; the paper's
+// other coarsest-level preconditioner, Sec. 4.3 smoother table):
+//   Dt_i = A_ii - sum_{j<i} A_ij A_ji / Dt_j, ascending j,
+// with A_ji read from the transposed values at the same position.  Serial in
+// one thread: the level has a few dozen rows, and this runs once per set of
+// coefficients.  ok = 0 when a pivot is not finite, changes sign against
+// A_ii, or falls below 1e-12 |A_ii|; the solve then uses the diagonal.
+__global__ void k_dic_factor(Sell A, double *dt, int *ok) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int good = 1;
+    for (int32_t i = 0; i < A.n; ++i) {
+        const int64_t ps = A.iperm ? (int64_t)A.iperm[i] : (int64_t)i;
+        const int w = row_len(A, ps);
+        double d = A.diag[i];
+        for (int k = 0; k < w; ++k) {
+            const int64_t e = entry_at(A, ps, k);
+            const int32_t c = A.col[e];
+            if (c < i) d = d - (A.val[e] * A.valT[e]) / dt[c];
+        }
+        dt[i] = d;
+        if (!isfinite(d) || !(fabs(d) > 1e-12 * fabs(A.diag[i])) || ((d > 0.0) != (A.diag[i] > 0.0)))
+            good = 0;
+    }
+    *ok = good;
+}
+
+static void ensure_dic(ldu_t *h, hipStream_t st) {
+    if (h->dic_ready) return;
+    Level &L = h->levels.back();
+    k_dic_factor<<<1, 1, 0, st>>>(L.A, h->dic_dt, h->flag);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(h->hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    h->dic_ok = *h->hflag != 0;
+    h->dic_ready = true;
 }
 
 // ---------------------------------------------------------------- V-cycle kernels
@@ -507,6 +547,38 @@ k_vc_resid(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
         if (p < A.n) {
             const int32_t i = sv_row<CMP>(A, p);
             t[i] = r[i] - sell_row<CMP>(A, s, lane, i, Direct<T>{e});
+        }
+    });
+}
+
+// one inner step of the two-stage Gauss-Seidel sweep (Berger-Vergiat et al.
+// 2021, the paper's second GPU smoother, Sec. 4.3):
+//   g_i = (t_i - sum_{j in tri(i)} A_ij src_j) / D_i
+// over the strictly lower (forward sweep) or strictly upper (backward sweep)
+// part of row i; src_j = t_j / D_j on the first step (SRC_T), else the
+// previous step's g.  mode 0 stores g; mode 1 sets e = g (a sweep from
+// zero); mode 2 adds g to e.
+template <typename T>
+struct DivDiag {
+    const T *t, *D;
+    __device__ __forceinline__ T operator()(int32_t j) const { return t[j] / D[j]; }
+};
+
+template <bool CMP, bool UPPER, bool SRC_T, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_gs(SellView<T> A, const T *__restrict__ t, const T *__restrict__ g, T *__restrict__ out,
+        int mode, const DevScalars *ds) {
+    if (vc_skip(ds)) return;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(A.nslices, [&](int64_t s) {
+        const int64_t p = s * kWave + lane;
+        if (p < A.n) {
+            const int32_t i = sv_row<CMP>(A, p);
+            T y;
+            if constexpr (SRC_T) y = sell_tri<CMP, UPPER>(A, s, lane, i, DivDiag<T>{t, A.diag});
+            else y = sell_tri<CMP, UPPER>(A, s, lane, i, Direct<T>{g});
+            const T gi = (t[i] - y) / A.diag[i];
+            out[i] = mode == 2 ? out[i] + gi : gi;
         }
     });
 }
@@ -588,7 +660,7 @@ __device__ __forceinline__ void bcast_sum(double (&v)[K]) {
     }
 }
 
-// LDS holds the coarsest CG vectors when 4 n doubles fit (dynamic shared memory)
+// LDS holds the coarsest CG vectors when 5 n doubles fit (dynamic shared memory)
 constexpr int kLdsCoarse = 1536;
 
 // a barrier also in the one-wavefront case (there it costs next to nothing
@@ -598,13 +670,45 @@ __device__ __forceinline__ void csync() {
     __syncthreads();
 }
 
+// DIC preconditioner z = M^-1 r by forward and backward substitution in row
+// form, serially (one thread): y_i = (r_i - sum_{j<i} A_ij y_j) / Dt_i for
+// ascending i, then z_i = y_i - (sum_{j>i} A_ij z_j) / Dt_i for descending i,
+// each row sum in column order
+__device__ void dic_serial(const SellView<double> &A, const double *__restrict__ dt,
+                           const double *__restrict__ r, double *__restrict__ z) {
+    const int32_t n = A.n;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t ps = sv_pos(A, i);
+        const int w = row_len(A, ps);
+        double sum = 0.0;
+        for (int k = 0; k < w; ++k) {
+            const int64_t e = entry_at(A, ps, k);
+            const int32_t c = A.col[e];
+            if (c < i) sum = sum + A.val[e] * z[c];
+        }
+        z[i] = (r[i] - sum) / dt[i];
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+        const int64_t ps = sv_pos(A, i);
+        const int w = row_len(A, ps);
+        double sum = 0.0;
+        for (int k = 0; k < w; ++k) {
+            const int64_t e = entry_at(A, ps, k);
+            const int32_t c = A.col[e];
+            if (c > i) sum = sum + A.val[e] * z[c];
+        }
+        z[i] = z[i] - sum / dt[i];
+    }
+}
+
 template <typename TI, int NW>
 __device__ void coarsest_body(const SellView<double> &A, const TI *__restrict__ rhs,
                               TI *__restrict__ eo, double *__restrict__ w, int singular,
-                              double tol, int max_it) {
+                              double tol, int max_it, const double *__restrict__ dt) {
     constexpr int NT = NW * kWave;
     const int32_t n = A.n;
-    double *r = w, *p = w + n, *q = w + 2 * (int64_t)n, *x = w + 3 * (int64_t)n;
+    double *r = w, *p = w + n, *q = w + 2 * (int64_t)n, *x = w + 3 * (int64_t)n,
+           *z = w + 4 * (int64_t)n;
     for (int32_t i = threadIdx.x; i < n; i += NT) {
         r[i] = (double)rhs[i];
         x[i] = 0.0;
@@ -618,16 +722,25 @@ __device__ void coarsest_body(const SellView<double> &A, const TI *__restrict__ 
         for (int32_t i = threadIdx.x; i < n; i += NT) r[i] = r[i] - mean;
         csync<NW>();
     }
+    // z = M^-1 r (diagonal, or DIC when dt is given); r is complete on entry
+    auto precond = [&]() {
+        if (dt) {
+            if (threadIdx.x == 0) dic_serial(A, dt, r, z);
+        } else {
+            for (int32_t i = threadIdx.x; i < n; i += NT) z[i] = r[i] / A.diag[i];
+        }
+        csync<NW>();
+    };
     double b2[1] = {0.0};
     for (int32_t i = threadIdx.x; i < n; i += NT) b2[0] += r[i] * r[i];
     bcast_sum<1, NW>(b2);
     const double bn = sqrt(b2[0]);
     if (bn > 0.0) {
+        precond();
         double rz[1] = {0.0};
         for (int32_t i = threadIdx.x; i < n; i += NT) {
-            const double zi = r[i] / A.diag[i];
-            p[i] = zi;
-            rz[0] += r[i] * zi;
+            p[i] = z[i];
+            rz[0] += r[i] * z[i];
         }
         bcast_sum<1, NW>(rz);
         double rho = rz[0];
@@ -642,25 +755,33 @@ __device__ void coarsest_body(const SellView<double> &A, const TI *__restrict__ 
             bcast_sum<1, NW>(pq);
             if (!isfinite(pq[0]) || fabs(pq[0]) <= 1e-300) break;
             const double alpha = rho / pq[0];
-            double acc[2] = {0.0, 0.0};
+            double rr[1] = {0.0};
             for (int32_t i = threadIdx.x; i < n; i += NT) {
                 x[i] = x[i] + alpha * p[i];
                 const double ri = r[i] - alpha * q[i];
                 r[i] = ri;
-                acc[0] += ri * ri;
-                acc[1] += ri * (ri / A.diag[i]);
+                rr[0] += ri * ri;
             }
-            bcast_sum<2, NW>(acc);
-            if (sqrt(acc[0]) / bn <= tol) break;
-            const double beta = acc[1] / rho;
-            rho = acc[1];
-            for (int32_t i = threadIdx.x; i < n; i += NT)
-                p[i] = r[i] / A.diag[i] + beta * p[i];
+            bcast_sum<1, NW>(rr);
+            if (sqrt(rr[0]) / bn <= tol) break;
+            precond();
+            double rzn[1] = {0.0};
+            for (int32_t i = threadIdx.x; i < n; i += NT) rzn[0] += r[i] * z[i];
+            bcast_sum<1, NW>(rzn);
+            const double beta = rzn[0] / rho;
+            rho = rzn[0];
+            for (int32_t i = threadIdx.x; i < n; i += NT) p[i] = z[i] + beta * p[i];
             csync<NW>();
         }
     }
     csync<NW>();
     for (int32_t i = threadIdx.x; i < n; i += NT) eo[i] = (TI)x[i];
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int j) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), j);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), j);
+    return __hiloint2double(hi, lo);
 }
 
 
@@ -675,15 +796,15 @@ __global__ void __launch_bounds__(kWave)
 k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
                 const float *__restrict__ rhs_f, double *__restrict__ eo_d,
                 float *__restrict__ eo_f, int singular, double tol, int max_it,
-                const DevScalars *ds) {
+                const double *__restrict__ dt, const DevScalars *ds) {
     __shared__ int32_t cL[kWaveRow * kWave];
     __shared__ double vL[kWaveRow * kWave];
     __shared__ double p[kWave];
     if (vc_skip(ds)) return;
     const int32_t n = A.n;
     const int i = threadIdx.x;
-    double di = 1.0, ri = 0.0;
-    int m = 0;
+    double di = 1.0, ri = 0.0, rdt = 0.0;
+    int m = 0, nl = 0;  // entries of row i, and how many lie left of the diagonal
     if (i < n) {
         const int64_t ps = sv_pos(A, i);
         const int w = row_len(A, ps);
@@ -693,11 +814,46 @@ k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
             if (c == i) continue;  // padding entries point at the row
             cL[m * kWave + i] = c;
             vL[m * kWave + i] = A.val[e];
+            nl += c < i;
             ++m;
         }
         di = A.diag[i];
         ri = rhs_d ? rhs_d[i] : (double)rhs_f[i];
+        if (dt) rdt = 1.0 / dt[i];
     }
+    __syncthreads();
+    // z = M^-1 r: the diagonal, or the DIC factor by column-oriented
+    // substitution: at step j lane j's value is final and is broadcast, and
+    // every row holding column j takes its term (lower entries in ascending
+    // column order on the way down, upper entries in descending order on the
+    // way up)
+    auto precond = [&](double rv) -> double {
+        if (!dt) return (i < n) ? rv / di : 0.0;
+        double acc = 0.0, y = 0.0;
+        int kk = 0;
+        for (int j = 0; j < n; ++j) {
+            const double cand = (rv - acc) * rdt;
+            const double yj = readlane_f64(cand, j);
+            if (i == j) y = cand;
+            if (kk < nl && cL[kk * kWave + i] == j) {
+                acc = acc + vL[kk * kWave + i] * yj;
+                ++kk;
+            }
+        }
+        acc = 0.0;
+        double zv = 0.0;
+        kk = m - 1;
+        for (int j = n - 1; j >= 0; --j) {
+            const double cand = y - acc * rdt;
+            const double zj = readlane_f64(cand, j);
+            if (i == j) zv = cand;
+            if (kk >= nl && cL[kk * kWave + i] == j) {
+                acc = acc + vL[kk * kWave + i] * zj;
+                --kk;
+            }
+        }
+        return (i < n) ? zv : 0.0;
+    };
     if (singular) {
         const double mean = wave_sum(ri) / (double)n;
         if (i < n) ri = ri - mean;
@@ -705,7 +861,7 @@ k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
     double xi = 0.0;
     const double bn = sqrt(wave_sum(ri * ri));
     if (bn > 0.0) {
-        double pi = (i < n) ? ri / di : 0.0;
+        double pi = precond(ri);
         double rho = wave_sum(ri * pi);
         for (int it = 0; it < max_it; ++it) {
             p[i] = pi;
@@ -721,7 +877,7 @@ k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
             const double alpha = rho / pq;
             xi = xi + alpha * pi;
             ri = ri - alpha * qi;
-            const double zi = (i < n) ? ri / di : 0.0;
+            const double zi = precond(ri);
             const double rr = wave_sum(ri * ri);
             const double rz = wave_sum(ri * zi);
             if (sqrt(rr) / bn <= tol) break;
@@ -740,10 +896,11 @@ k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
 template <typename TI, int NW>
 __global__ void __launch_bounds__(kBlock)
 k_coarsest(SellView<double> A, const TI *__restrict__ rhs, TI *__restrict__ eo,
-           double *__restrict__ w, int singular, double tol, int max_it, const DevScalars *ds) {
+           double *__restrict__ w, int singular, double tol, int max_it,
+           const double *__restrict__ dt, const DevScalars *ds) {
     extern __shared__ double lds_w[];
     if (vc_skip(ds)) return;
-    coarsest_body<TI, NW>(A, rhs, eo, A.n <= kLdsCoarse ? lds_w : w, singular, tol, max_it);
+    coarsest_body<TI, NW>(A, rhs, eo, A.n <= kLdsCoarse ? lds_w : w, singular, tol, max_it, dt);
 }
 
 // x += e (GAMG correction of the outer FP64 loop)
@@ -791,13 +948,50 @@ static void launch_jacobi(const SellView<T> &A, const T *r, const T *e, T *eo, T
     else k_vc_jacobi<false, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, ds);
 }
 
+template <bool CMP, bool UPPER, typename T>
+static void launch_gs_step(const SellView<T> &A, const T *t, const T *g, T *out, int mode,
+                           const DevScalars *ds, int G, hipStream_t st) {
+    if (g) k_vc_gs<CMP, UPPER, false, T><<<G, kBlock, 0, st>>>(A, t, g, out, mode, ds);
+    else k_vc_gs<CMP, UPPER, true, T><<<G, kBlock, 0, st>>>(A, t, g, out, mode, ds);
+}
+
+// one two-stage Gauss-Seidel sweep on A e = r: t = r - A e (t = r from
+// zero), `inner` triangular Jacobi-Richardson steps through the ping-pong
+// buffers w0, w1, the last one updating e in place (each row reads only t,
+// the previous step and its own e entry)
+template <typename T>
+static void gs_sweep(const SellView<T> &A, const T *r, T *e, T *t, T *w0, T *w1, bool from_zero,
+                     bool backward, int inner, const DevScalars *ds, int G, hipStream_t st) {
+    const T *tt = r;
+    if (!from_zero) {
+        if (A.pdeg) k_vc_resid<true, T><<<G, kBlock, 0, st>>>(A, r, e, t, ds);
+        else k_vc_resid<false, T><<<G, kBlock, 0, st>>>(A, r, e, t, ds);
+        tt = t;
+    }
+    const T *g = nullptr;
+    for (int k = 0; k < inner; ++k) {
+        const bool last = k + 1 == inner;
+        T *out = last ? e : (k % 2 == 0 ? w0 : w1);
+        const int mode = last ? (from_zero ? 1 : 2) : 0;
+        if (A.pdeg) {
+            if (backward) launch_gs_step<true, true, T>(A, tt, g, out, mode, ds, G, st);
+            else launch_gs_step<true, false, T>(A, tt, g, out, mode, ds, G, st);
+        } else {
+            if (backward) launch_gs_step<false, true, T>(A, tt, g, out, mode, ds, G, st);
+            else launch_gs_step<false, false, T>(A, tt, g, out, mode, ds, G, st);
+        }
+        g = out;
+    }
+}
+
 // ---------------------------------------------------------------- V-cycle driver
 struct VCtx {
     ldu_t *h;
     const ldu_gamg_opts *o;
     bool tr;
     hipStream_t st;
-    double *cw;  // coarsest scratch, 4 n_coarsest doubles
+    double *cw;        // coarsest scratch, 5 n_coarsest doubles
+    const double *dt;  // coarsest DIC pivots, or null for the diagonal
 };
 
 template <typename T>
@@ -811,11 +1005,12 @@ template <typename T>
 static T *lvec(Level &L, int which);
 template <>
 double *lvec<double>(Level &L, int which) {
-    return which == 0 ? L.r : which == 1 ? L.e : which == 2 ? L.e2 : L.t;
+    return which == 0 ? L.r : which == 1 ? L.e : which == 2 ? L.e2 : which == 3 ? L.t : L.w;
 }
 template <>
 float *lvec<float>(Level &L, int which) {
-    return which == 0 ? L.r32 : which == 1 ? L.e32 : which == 2 ? L.e232 : L.t32;
+    return which == 0 ? L.r32 : which == 1 ? L.e32 : which == 2 ? L.e232 : which == 3 ? L.t32
+                                                                                     : L.w32;
 }
 
 template <typename T>
@@ -826,17 +1021,17 @@ static T *vcycle(const VCtx &c, size_t l, const T *r) {
     T *e = lvec<T>(L, 1), *e2 = lvec<T>(L, 2), *t = lvec<T>(L, 3);
     if (l + 1 == h->levels.size()) {
         const int maxit = std::max(2 * L.n, 100);
-        const size_t lds = L.n <= kLdsCoarse ? sizeof(double) * 4 * L.n : 0;
+        const size_t lds = L.n <= kLdsCoarse ? sizeof(double) * 5 * L.n : 0;
         if (L.n <= kWave && L.max_row <= kWaveRow) {
             const bool f64 = sizeof(T) == sizeof(double);
             k_coarsest_wave<<<1, kWave, 0, st>>>(
                 L.A.view(c.tr), f64 ? (const double *)r : nullptr,
                 f64 ? nullptr : (const float *)r, f64 ? (double *)e : nullptr,
-                f64 ? nullptr : (float *)e, L.singular, kCoarsestTol, maxit, h->dev);
+                f64 ? nullptr : (float *)e, L.singular, kCoarsestTol, maxit, c.dt, h->dev);
         } else
             k_coarsest<T, kWavesPerBlock><<<1, kBlock, lds, st>>>(L.A.view(c.tr), r, e, c.cw,
                                                                  L.singular, kCoarsestTol,
-                                                                 maxit, h->dev);
+                                                                 maxit, c.dt, h->dev);
         HIP_CHECK(hipGetLastError());
         return e;
     }
@@ -844,11 +1039,19 @@ static T *vcycle(const VCtx &c, size_t l, const T *r) {
     const int64_t S = L.A.nslices;
     const int G = stream_grid_slices(S);
     const T omega = (T)c.o->omega;
-    if (c.o->n_pre > 0) k_vc_first<T><<<G, kBlock, 0, st>>>(L.n, S, r, A.diag, e, omega, h->dev);
-    else k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
-    for (int k = 1; k < c.o->n_pre; ++k) {
-        launch_jacobi<T>(A, r, e, e2, omega, h->dev, G, st);
-        std::swap(e, e2);
+    const bool gs = c.o->smoother == LDU_SMOOTH_GS2;
+    T *w1 = lvec<T>(L, 4);
+    if (gs) {  // forward two-stage Gauss-Seidel sweeps, the first from e = 0
+        if (c.o->n_pre == 0) k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
+        for (int k = 0; k < c.o->n_pre; ++k)
+            gs_sweep<T>(A, r, e, t, e2, w1, k == 0, false, c.o->gs_inner, h->dev, G, st);
+    } else {
+        if (c.o->n_pre > 0) k_vc_first<T><<<G, kBlock, 0, st>>>(L.n, S, r, A.diag, e, omega, h->dev);
+        else k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
+        for (int k = 1; k < c.o->n_pre; ++k) {
+            launch_jacobi<T>(A, r, e, e2, omega, h->dev, G, st);
+            std::swap(e, e2);
+        }
     }
     if (A.pdeg) k_vc_resid<true, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
     else k_vc_resid<false, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
@@ -863,8 +1066,12 @@ static T *vcycle(const VCtx &c, size_t l, const T *r) {
     }
     k_vc_correct<T><<<G, kBlock, 0, st>>>(L.n, S, ec, L.agg, e, c.o->scale_correction, h->dev);
     for (int k = 0; k < c.o->n_post; ++k) {
-        launch_jacobi<T>(A, r, e, e2, omega, h->dev, G, st);
-        std::swap(e, e2);
+        if (gs) {  // backward sweeps: the V-cycle stays symmetric
+            gs_sweep<T>(A, r, e, t, e2, w1, false, true, c.o->gs_inner, h->dev, G, st);
+        } else {
+            launch_jacobi<T>(A, r, e, e2, omega, h->dev, G, st);
+            std::swap(e, e2);
+        }
     }
     HIP_CHECK(hipGetLastError());
     return e;
@@ -882,8 +1089,22 @@ static void ensure_work32(ldu_t *h, hipStream_t st) {
     }
 }
 
+// buffers and factors a cycle needs beyond the hierarchy: the second
+// ping-pong vector of the two-stage smoother (three or more inner steps) and
+// the DIC pivots of the coarsest level
 static VCtx make_ctx(ldu_t *h, const ldu_gamg_opts &o, bool tr, hipStream_t st) {
-    return VCtx{h, &o, tr, st, h->coarse_work};
+    if (o.smoother == LDU_SMOOTH_GS2 && o.gs_inner >= 3) {
+        for (auto &L : h->levels) {
+            if (!L.w) L.w = h->gamg_arena.get<double>(L.n);
+            if (!L.w32) L.w32 = h->gamg_arena.get<float>(L.n);
+        }
+    }
+    const double *dt = nullptr;
+    if (o.coarsest == LDU_COARSE_DIC) {
+        ensure_dic(h, st);
+        if (h->dic_ok) dt = h->dic_dt;
+    }
+    return VCtx{h, &o, tr, st, h->coarse_work, dt};
 }
 
 static void fill_level_stats(ldu_t *h, ldu_stats *stats) {

@@ -141,6 +141,10 @@ struct Level {
     // V-cycle work vectors
     double *r = nullptr, *e = nullptr, *e2 = nullptr, *t = nullptr;
     float *r32 = nullptr, *e32 = nullptr, *e232 = nullptr, *t32 = nullptr;
+    // second ping-pong buffer of the two-stage Gauss-Seidel inner steps
+    // (allocated when a cycle asks for three or more of them)
+    double *w = nullptr;
+    float *w32 = nullptr;
 };
 
 }  // namespace ldu
@@ -166,7 +170,10 @@ struct ldu_t {
     int hist_cap = 0;
     int *flag = nullptr;             // device error flag (validation)
     int *hflag = nullptr;            // pinned
-    double *coarse_work = nullptr;   // coarsest-level CG scratch (4 n doubles)
+    double *coarse_work = nullptr;   // coarsest-level CG scratch (5 n doubles)
+    double *dic_dt = nullptr;        // coarsest-level DIC pivots
+    bool dic_ready = false;          // dic_dt matches the current coarsest values
+    bool dic_ok = false;             // every pivot usable (else diagonal fallback)
 };
 
 namespace ldu {

@@ -46,7 +46,8 @@ class GamgOpts(C.Structure):
                 ("n_coarsest", C.c_int), ("n_pre", C.c_int), ("n_post", C.c_int),
                 ("max_levels", C.c_int), ("scale_correction", C.c_int),
                 ("match_rounds", C.c_int), ("precision", C.c_int), ("max_refine", C.c_int),
-                ("omega", C.c_double), ("passes", C.c_int)]
+                ("omega", C.c_double), ("passes", C.c_int), ("smoother", C.c_int),
+                ("gs_inner", C.c_int), ("coarsest", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -138,11 +139,19 @@ def pcg_opts(**kw) -> PcgOpts:
     return o
 
 
+SMOOTHERS = {"jacobi": 0, "gs2": 1}
+COARSEST = {"diag": 0, "dic": 1}
+
+
 def gamg_opts(**kw) -> GamgOpts:
     o = GamgOpts()
     lib().ldu_gamg_default_opts(C.byref(o))
     if "precision" in kw and isinstance(kw["precision"], str):
         kw["precision"] = LDU_MIXED if kw["precision"] == "mixed" else LDU_FP64
+    if isinstance(kw.get("smoother"), str):
+        kw["smoother"] = SMOOTHERS[kw["smoother"]]
+    if isinstance(kw.get("coarsest"), str):
+        kw["coarsest"] = COARSEST[kw["coarsest"]]
     for k, v in kw.items():
         setattr(o, k, v)
     return o

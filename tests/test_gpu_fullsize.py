@@ -135,11 +135,18 @@ def test_c5_adjoint_gradient():
         assert s.converged
         return inc.cpu().numpy()
 
+    # per face: 1e-5 relative, plus an absolute floor for faces whose gradient
+    # is orders of magnitude below the largest: x and lambda carry errors of
+    # about kappa * 1e-11 (kappa ~ 1e5 here), and each face gradient is a
+    # product of differences of them, so faces near max|g| * 1e-4 see that
+    # error at the 1e-7 * max|g| level
+    gmax = np.abs(gc).max()
     for f in c.meta["fd_faces"]:
         h = 1e-6 * c.upper[f]
         ap = c.upper.copy(); ap[f] += h
         am = c.upper.copy(); am[f] -= h
         dp, dm = increment(ap), increment(am)
         fd = (dx @ (dp - dm) + 0.5 * (dp @ dp - dm @ dm)) / (2 * h)
-        assert abs(fd - gc[f]) <= 1e-5 * abs(gc[f]) + 1e-9 * np.abs(gc).max(), (f, fd, gc[f])
+        print(f"face {f}: adjoint {gc[f]:.9e} fd {fd:.9e}")
+        assert abs(fd - gc[f]) <= 1e-5 * abs(gc[f]) + 1e-7 * gmax, (f, fd, gc[f])
     m.close()

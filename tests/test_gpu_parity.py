@@ -234,6 +234,59 @@ def test_aggressive_agglomeration_solves_match_oracle(passes):
     assert np.linalg.norm(x3.cpu().numpy() - r3.x) <= 1e-9 * np.linalg.norm(r3.x)
 
 
+CYCLES = [("gs2", 1, "diag"), ("gs2", 2, "diag"), ("gs2", 3, "dic"), ("jacobi", 1, "dic")]
+
+
+@pytest.mark.parametrize("smoother,inner,coarsest", CYCLES)
+def test_cycle_variants_match_oracle(smoother, inner, coarsest):
+    """Two-stage Gauss-Seidel smoothing and the DIC coarsest preconditioner:
+    one V-cycle, the GAMG solve and CG + V-cycle against the oracle."""
+    kw = dict(smoother=smoother, gs_inner=inner, coarsest=coarsest)
+    c = _gamg_case("c5s")
+    A = O.Ldu.from_case(c)
+    g = O.Gamg(A, **kw)
+    m = _lib().from_case(c)
+    r = np.random.default_rng(9).standard_normal(c.n_cells)
+    e = m.vcycle(_t(r), **kw).cpu().numpy()
+    ref = g.vcycle(r)
+    assert np.linalg.norm(e - ref) <= 1e-11 * np.linalg.norm(ref)
+    x, st = m.gamg(_t(c.rhs[0]), rel_tol=1e-8, history=300, **kw)
+    rs = g.solve(c.rhs[0], tol=1e-8)
+    assert st.converged and st.iterations == rs.iterations
+    assert hist_close(st.history, rs.history)
+    assert np.linalg.norm(x.cpu().numpy() - rs.x) <= 1e-10 * np.linalg.norm(rs.x)
+    m.gamg_setup(n_pre=1, n_post=1, **kw)
+    xp, sp = m.pcg(_t(c.rhs[0]), precond=2, rel_tol=1e-8)
+    rp = g.pcg(c.rhs[0], tol=1e-8, n_pre=1, n_post=1)
+    assert sp.converged and sp.iterations == rp.iterations
+    assert np.linalg.norm(xp.cpu().numpy() - rp.x) <= 1e-9 * np.linalg.norm(rp.x)
+    # mixed: FP32 V-cycles with the same smoother, refined to 1e-12
+    xm, sm = m.gamg(_t(c.rhs[0]), rel_tol=1e-12, precision="mixed", **kw)
+    assert sm.converged and true_res(c, xm.cpu().numpy()) <= 1e-12
+
+
+def test_dic_on_a_large_coarsest_level_and_singular_fallback():
+    """A coarsest level too large for the one-wavefront kernel takes the
+    workgroup kernel's serial substitution; a singular coarsest level (pure
+    zero gradient) may lose its last pivot and then falls back to the
+    diagonal, as the oracle does."""
+    for name, ncoarse in (("c5s", 400), ("c2s", 50)):
+        c = _gamg_case(name)
+        A = O.Ldu.from_case(c)
+        g = O.Gamg(A, n_coarsest=ncoarse, coarsest="dic")
+        m = _lib().from_case(c)
+        x, st = m.gamg(_t(c.rhs[0]), rel_tol=1e-8, n_coarsest=ncoarse, coarsest="dic",
+                       history=300)
+        rs = g.solve(c.rhs[0], tol=1e-8)
+        assert st.n_levels == g.n_levels
+        assert st.converged and st.iterations == rs.iterations, name
+        assert hist_close(st.history, rs.history)
+        xg, xr = x.cpu().numpy(), rs.x
+        if c.singular:
+            xg, xr = xg - xg.mean(), xr - xr.mean()
+        assert np.linalg.norm(xg - xr) <= 1e-10 * np.linalg.norm(xr)
+
+
 @pytest.mark.parametrize("solver", ["pcg", "gamg", "pcg_gamg"])
 def test_mixed_refines_to_fp64(solver):
     c = _gamg_case("c5s") if solver == "gamg" else CASES["ragged"]

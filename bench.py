@@ -119,6 +119,8 @@ def main():
                     help="Jacobi sweeps before and after the coarse correction")
     ap.add_argument("--amul-only", action="store_true",
                     help="only the Amul and copy timings (for counter runs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the mixed, adjoint and variant solves (for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -196,80 +198,84 @@ def main():
     assert st.converged and res <= 1e-8, (st, res)
     t_step = float(np.mean(times))
 
-    # the mixed form of the same solve: FP64 refinement around FP32 CG with an
-    # FP32 V-cycle preconditioner (one warm-up, then the same step count)
-    mopts = dict(opts, precision="mixed")
-    m.pcg(b, **mopts)
-    mtimes = []
-    for k in range(args.steps):
+    variants, mixed_rec, adj_rec = {}, None, None
+    if not args.no_extra:
+        # the mixed form of the same solve: FP64 refinement around FP32 CG with an
+        # FP32 V-cycle preconditioner (one warm-up, then the same step count)
+        mopts = dict(opts, precision="mixed")
+        m.pcg(b, **mopts)
+        mtimes = []
+        for k in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xm, sm = m.pcg(b, **mopts)
+            torch.cuda.synchronize()
+            mtimes.append(time.perf_counter() - t0)
+        mres = m.residual(b, xm)
+        assert sm.converged and mres <= 1e-8, (sm, mres)
+        log(f"[bench] mixed: {np.mean(mtimes):.4f} s, {sm.refinements} refinements, "
+            f"{sm.iterations} inner iterations, true residual {mres:.3e}")
+        mixed_rec = {"s": float(np.mean(mtimes)), "refinements": sm.refinements,
+                     "inner_iterations": sm.iterations, "true_residual": mres,
+                     "solver": "FP64 refinement, FP32 CG + FP32 V-cycle (FP64 coarsest)"}
+
+        # the adjoint form: lambda = A^-T (x - x_t) with the same preconditioned CG
+        # (on the transposed values of every level), then the per-face gradients
+        xt = torch.randn(case.n_cells, dtype=torch.float64, device=dev,
+                         generator=torch.Generator(device=dev).manual_seed(4))
+        g = xs - xt
+        m.adjoint(g, **opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xm, sm = m.pcg(b, **mopts)
+        lam, sa = m.adjoint(g, **opts)
         torch.cuda.synchronize()
-        mtimes.append(time.perf_counter() - t0)
-    mres = m.residual(b, xm)
-    assert sm.converged and mres <= 1e-8, (sm, mres)
-    log(f"[bench] mixed: {np.mean(mtimes):.4f} s, {sm.refinements} refinements, "
-        f"{sm.iterations} inner iterations, true residual {mres:.3e}")
+        t_adj = time.perf_counter() - t0
+        gd, gu, gl = m.coeff_grad(lam, xs)
+        t_grad = time_kernel(lambda: m.coeff_grad(lam, xs), 20, torch)
+        assert sa.converged
+        log(f"[bench] adjoint: {t_adj:.4f} s, {sa.iterations} iterations; coeff_grad "
+            f"{t_grad * 1e6:.0f} us")
+        adj_rec = {"solve_s": t_adj, "iterations": sa.iterations,
+                   "coeff_grad_us": t_grad * 1e6,
+                   "coeff_grad_GBps": amul_bytes(case.n_cells, case.n_faces) / t_grad / 1e9}
 
-    # the adjoint form: lambda = A^-T (x - x_t) with the same preconditioned CG
-    # (on the transposed values of every level), then the per-face gradients
-    xt = torch.randn(case.n_cells, dtype=torch.float64, device=dev,
-                     generator=torch.Generator(device=dev).manual_seed(4))
-    g = xs - xt
-    m.adjoint(g, **opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lam, sa = m.adjoint(g, **opts)
-    torch.cuda.synchronize()
-    t_adj = time.perf_counter() - t0
-    gd, gu, gl = m.coeff_grad(lam, xs)
-    t_grad = time_kernel(lambda: m.coeff_grad(lam, xs), 20, torch)
-    assert sa.converged
-    log(f"[bench] adjoint: {t_adj:.4f} s, {sa.iterations} iterations; coeff_grad "
-        f"{t_grad * 1e6:.0f} us")
-
-    # variants of the same solve (each one warm-up, then the mean of two):
-    # aggressive agglomeration (two and three matching passes per level), the
-    # two-stage Gauss-Seidel smoother, the DIC coarsest preconditioner
-    variants = {}
-    for name, kw in (("aggressive_2pass", dict(passes=2)),
-                     ("aggressive_3pass", dict(passes=3)),
-                     ("gs2_smoother", dict(smoother="gs2")),
-                     ("dic_coarsest", dict(coarsest="dic")),
-                     ("aggressive_2pass_gs2", dict(passes=2, smoother="gs2"))):
-        t0 = time.perf_counter()
-        m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, **kw)
-        torch.cuda.synchronize()
-        ts = time.perf_counter() - t0
-        rec = {"setup_s": ts, "levels": m.n_levels()}
-        for prec in ("fp64", "mixed"):
-            vo = dict(opts, precision=prec)
-            m.pcg(b, **vo)
-            vt = []
-            for _ in range(2):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                xv, sv = m.pcg(b, **vo)
-                torch.cuda.synchronize()
-                vt.append(time.perf_counter() - t0)
-            vres = m.residual(b, xv)
-            assert sv.converged and vres <= 1e-8, (name, prec, sv, vres)
-            rec[prec] = {"s": float(np.mean(vt)), "iterations": sv.iterations,
-                         "refinements": sv.refinements, "true_residual": vres}
-        variants[name] = rec
-        log(f"[bench] variant {name}: {rec['levels']} levels, fp64 {rec['fp64']['s']:.4f} s "
-            f"({rec['fp64']['iterations']} it), mixed {rec['mixed']['s']:.4f} s")
-    m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
+        # variants of the same solve (each one warm-up, then the mean of two):
+        # aggressive agglomeration (two and three matching passes per level), the
+        # two-stage Gauss-Seidel smoother, the DIC coarsest preconditioner
+        variants = {}
+        for name, kw in (("aggressive_2pass", dict(passes=2)),
+                         ("aggressive_3pass", dict(passes=3)),
+                         ("gs2_smoother", dict(smoother="gs2")),
+                         ("dic_coarsest", dict(coarsest="dic")),
+                         ("aggressive_2pass_gs2", dict(passes=2, smoother="gs2"))):
+            t0 = time.perf_counter()
+            m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, **kw)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            rec = {"setup_s": ts, "levels": m.n_levels()}
+            for prec in ("fp64", "mixed"):
+                vo = dict(opts, precision=prec)
+                m.pcg(b, **vo)
+                vt = []
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    xv, sv = m.pcg(b, **vo)
+                    torch.cuda.synchronize()
+                    vt.append(time.perf_counter() - t0)
+                vres = m.residual(b, xv)
+                assert sv.converged and vres <= 1e-8, (name, prec, sv, vres)
+                rec[prec] = {"s": float(np.mean(vt)), "iterations": sv.iterations,
+                             "refinements": sv.refinements, "true_residual": vres}
+            variants[name] = rec
+            log(f"[bench] variant {name}: {rec['levels']} levels, fp64 {rec['fp64']['s']:.4f} s "
+                f"({rec['fp64']['iterations']} it), mixed {rec['mixed']['s']:.4f} s")
+        m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
 
     extra = {
         "variants": variants,
-        "adjoint": {"solve_s": t_adj, "iterations": sa.iterations,
-                    "coeff_grad_us": t_grad * 1e6,
-                    "coeff_grad_GBps": amul_bytes(case.n_cells, case.n_faces) / t_grad / 1e9},
-        "mixed_solve": {"s": float(np.mean(mtimes)), "refinements": sm.refinements,
-                        "inner_iterations": sm.iterations, "true_residual": mres,
-                        "solver": "FP64 refinement, FP32 CG + FP32 V-cycle (FP64 coarsest)"},
+        "adjoint": adj_rec,
+        "mixed_solve": mixed_rec,
         "setup_s": {"ldu_create": t_create, "gamg_setup": t_setup},
         "levels": nlev,
         "iterations": st.iterations,

@@ -518,21 +518,27 @@ k_vc_zero(int32_t n, int64_t S, T *__restrict__ e, const DevScalars *ds) {
     });
 }
 
-// e_out = e + omega (r - A e) / D
-template <bool CMP, typename T>
+// e_out = e + omega (r - A e) / D; DOT also accumulates the block partials of
+// rdot . e_out (the preconditioned CG's r . z, saving a pass over both)
+template <bool CMP, bool DOT, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
-            T *__restrict__ eo, T omega, const DevScalars *ds) {
+            T *__restrict__ eo, T omega, const T *__restrict__ rdot, double *partials,
+            const DevScalars *ds) {
     if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
+    double acc[1] = {0.0};
     for_each_slice(A.nslices, [&](int64_t s) {
         const int64_t p = s * kWave + lane;
         if (p < A.n) {
             const int32_t i = sv_row<CMP>(A, p);
             const T y = sell_row<CMP>(A, s, lane, i, Direct<T>{e});
-            eo[i] = e[i] + omega * (r[i] - y) / A.diag[i];
+            const T zi = e[i] + omega * (r[i] - y) / A.diag[i];
+            eo[i] = zi;
+            if constexpr (DOT) acc[0] += (double)rdot[i] * (double)zi;
         }
     });
+    if constexpr (DOT) block_partials<1>(acc, partials);
 }
 
 // t = r - A e
@@ -941,11 +947,18 @@ k_refine_add(int32_t n, int64_t S, const float *__restrict__ d, double *__restri
     });
 }
 
+// one Jacobi sweep; with rdot, also the block partials of rdot . e_out
 template <typename T>
 static void launch_jacobi(const SellView<T> &A, const T *r, const T *e, T *eo, T omega,
-                          const DevScalars *ds, int G, hipStream_t st) {
-    if (A.pdeg) k_vc_jacobi<true, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, ds);
-    else k_vc_jacobi<false, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, ds);
+                          const T *rdot, double *partials, const DevScalars *ds, int G,
+                          hipStream_t st) {
+    if (A.pdeg) {
+        if (rdot) k_vc_jacobi<true, true, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, ds);
+        else k_vc_jacobi<true, false, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, ds);
+    } else {
+        if (rdot) k_vc_jacobi<false, true, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, ds);
+        else k_vc_jacobi<false, false, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, ds);
+    }
 }
 
 template <bool CMP, bool UPPER, typename T>
@@ -1013,8 +1026,13 @@ float *lvec<float>(Level &L, int which) {
                                                                                      : L.w32;
 }
 
+// one V-cycle e = V(l, r); returns the buffer holding e.  With rdot, the last
+// level-l kernel also leaves the block partials of rdot . e in h->partials
+// and *dotted is set (only when that last kernel is a Jacobi sweep).
 template <typename T>
-static T *vcycle(const VCtx &c, size_t l, const T *r) {
+static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
+                 bool *dotted = nullptr) {
+    if (dotted) *dotted = false;
     ldu_t *h = c.h;
     Level &L = h->levels[l];
     hipStream_t st = c.st;
@@ -1049,7 +1067,7 @@ static T *vcycle(const VCtx &c, size_t l, const T *r) {
         if (c.o->n_pre > 0) k_vc_first<T><<<G, kBlock, 0, st>>>(L.n, S, r, A.diag, e, omega, h->dev);
         else k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
         for (int k = 1; k < c.o->n_pre; ++k) {
-            launch_jacobi<T>(A, r, e, e2, omega, h->dev, G, st);
+            launch_jacobi<T>(A, r, e, e2, omega, nullptr, nullptr, h->dev, G, st);
             std::swap(e, e2);
         }
     }
@@ -1068,9 +1086,12 @@ static T *vcycle(const VCtx &c, size_t l, const T *r) {
     for (int k = 0; k < c.o->n_post; ++k) {
         if (gs) {  // backward sweeps: the V-cycle stays symmetric
             gs_sweep<T>(A, r, e, t, e2, w1, false, true, c.o->gs_inner, h->dev, G, st);
-        } else {
-            launch_jacobi<T>(A, r, e, e2, omega, h->dev, G, st);
+        } else {  // the last sweep may also take the caller's dot product
+            const bool last = k + 1 == c.o->n_post;
+            launch_jacobi<T>(A, r, e, e2, omega, last ? rdot : nullptr, h->partials, h->dev, G,
+                             st);
             std::swap(e, e2);
+            if (last && rdot && dotted) *dotted = true;
         }
     }
     HIP_CHECK(hipGetLastError());
@@ -1300,8 +1321,9 @@ int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, b
                 k_pg_update<<<G, kBlock, 0, st>>>(n, S, x, h->r, h->p, h->q, h->partials,
                                                   h->dev);
                 launch_converge(h, G, false, st);
-                z = vcycle<double>(c, 0, h->r);
-                k_pg_rz<<<G, kBlock, 0, st>>>(n, S, h->r, z, h->partials, h->dev);
+                bool dotted = false;
+                z = vcycle<double>(c, 0, h->r, h->r, &dotted);
+                if (!dotted) k_pg_rz<<<G, kBlock, 0, st>>>(n, S, h->r, z, h->partials, h->dev);
                 launch_finalize<1>(h->partials, G, h->dev, EpiBeta{}, st);
                 k_pg_p<<<G, kBlock, 0, st>>>(n, S, z, h->p, h->dev);
             }

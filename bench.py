@@ -240,14 +240,15 @@ def main():
                    "coeff_grad_GBps": amul_bytes(case.n_cells, case.n_faces) / t_grad / 1e9}
 
         # variants of the same solve (each one warm-up, then the mean of two):
-        # aggressive agglomeration (two and three matching passes per level), the
-        # two-stage Gauss-Seidel smoother, the DIC coarsest preconditioner
+        # aggressive agglomeration (two or three matching passes per level, or
+        # three below a pairwise first level), the two-stage Gauss-Seidel
+        # smoother, the DIC coarsest preconditioner
         variants = {}
         for name, kw in (("aggressive_2pass", dict(passes=2)),
                          ("aggressive_3pass", dict(passes=3)),
+                         ("aggressive_3pass_below_level1", dict(passes=3, aggressive_from=1)),
                          ("gs2_smoother", dict(smoother="gs2")),
-                         ("dic_coarsest", dict(coarsest="dic")),
-                         ("aggressive_2pass_gs2", dict(passes=2, smoother="gs2"))):
+                         ("dic_coarsest", dict(coarsest="dic"))):
             t0 = time.perf_counter()
             m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, **kw)
             torch.cuda.synchronize()

@@ -75,7 +75,8 @@ typedef struct {
     int precond;          /* 0 none, 1 diagonal, 2 one GAMG V-cycle (the handle's
                              hierarchy and sweep settings from gamg_setup, or the
                              defaults; correction scaling off so that the
-                             preconditioner is symmetric; FP32 V-cycle in MIXED) */
+                             preconditioner is symmetric, which also needs
+                             n_pre == n_post; FP32 V-cycle in MIXED) */
     int precision;        /* LDU_FP64 or LDU_MIXED */
     int max_refine;       /* MIXED: outer refinement steps */
     int inner_max_iter;   /* MIXED: FP32 CG iterations per refinement */
@@ -86,7 +87,7 @@ typedef struct {
 /* Options of gamg_setup / gamg_solve.  Defaults (ldu_gamg_default_opts):
  * rel_tol 1e-8, max_cycles 200, n_coarsest 50, n_pre 2, n_post 2,
  * max_levels 50, scale_correction 1, match_rounds 16, precision LDU_FP64,
- * max_refine 200, omega 0.75, passes 1, smoother LDU_SMOOTH_JACOBI,
+ * max_refine 200, omega 0.75, passes 1, aggressive_from 0, smoother LDU_SMOOTH_JACOBI,
  * gs_inner 1, coarsest LDU_COARSE_DIAG. */
 typedef struct {
     double rel_tol;
@@ -106,6 +107,8 @@ typedef struct {
                             * 2^passes cells and the hierarchy has fewer levels
                             * (aggressive agglomeration, the remedy the paper
                             * points to for GAMG's many tiny levels, Sec. 4.4) */
+    int aggressive_from;   /* first level coarsened with `passes` passes; finer
+                            * levels keep one pass (0: every level) */
     int smoother;          /* LDU_SMOOTH_JACOBI: damped Jacobi (Richardson) with
                             * omega; LDU_SMOOTH_GS2: two-stage Gauss-Seidel
                             * (Berger-Vergiat et al. 2021): each sweep corrects

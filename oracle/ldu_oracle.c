@@ -713,6 +713,15 @@ orc_gamg *orc_gamg_build2(int32_t n, int64_t nf, const int32_t *own,
                           const double *upper, const double *lower,
                           int n_coarsest, int max_levels, int match_rounds,
                           int passes) {
+    return orc_gamg_build3(n, nf, own, nb, diag, upper, lower, n_coarsest,
+                           max_levels, match_rounds, passes, 0);
+}
+
+orc_gamg *orc_gamg_build3(int32_t n, int64_t nf, const int32_t *own,
+                          const int32_t *nb, const double *diag,
+                          const double *upper, const double *lower,
+                          int n_coarsest, int max_levels, int match_rounds,
+                          int passes, int aggressive_from) {
     orc_gamg *h = xcalloc(1, sizeof(orc_gamg));
     h->smoother = ORC_SMOOTH_JACOBI;
     h->gs_inner = 1;
@@ -736,7 +745,8 @@ orc_gamg *orc_gamg_build2(int32_t n, int64_t nf, const int32_t *own,
     while (h->nlev < max_levels) {
         olevel *L = &h->lev[h->nlev - 1];
         if (L->n <= n_coarsest) break;
-        int32_t nc = agglomerate_passes(L, match_rounds, passes);
+        int32_t nc = agglomerate_passes(L, match_rounds,
+                                        h->nlev - 1 >= aggressive_from ? passes : 1);
         if (100 * (int64_t)nc > 95 * (int64_t)L->n) {
             free(L->agg); free(L->partner); free(L->join);
             L->agg = L->partner = L->join = NULL;

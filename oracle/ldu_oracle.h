@@ -76,6 +76,13 @@ orc_gamg *orc_gamg_build2(int32_t n, int64_t nf, const int32_t *own,
                           const double *upper, const double *lower,
                           int n_coarsest, int max_levels, int match_rounds,
                           int passes);
+/* as build2, with the extra passes only on levels >= aggressive_from (the
+ * finer levels keep pairwise agglomeration) */
+orc_gamg *orc_gamg_build3(int32_t n, int64_t nf, const int32_t *own,
+                          const int32_t *nb, const double *diag,
+                          const double *upper, const double *lower,
+                          int n_coarsest, int max_levels, int match_rounds,
+                          int passes, int aggressive_from);
 void orc_gamg_free(orc_gamg *h);
 /* cycle variants: smoother (Jacobi, or two-stage Gauss-Seidel with gs_inner
  * inner steps) and the coarsest-level CG preconditioner (diagonal or DIC) */

@@ -77,6 +77,8 @@ def lib():
     L.orc_gamg_build2.restype = vp
     L.orc_gamg_build2.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p,
                                   C.c_int, C.c_int, C.c_int, C.c_int]
+    L.orc_gamg_build3.restype = vp
+    L.orc_gamg_build3.argtypes = L.orc_gamg_build2.argtypes + [C.c_int]
     L.orc_gamg_free.argtypes = [vp]
     L.orc_gamg_set_cycle.argtypes = [vp, C.c_int, C.c_int, C.c_int]
     L.orc_gs2_sweep.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p,
@@ -216,14 +218,15 @@ class Gamg:
     COARSEST = {"diag": 0, "dic": 1}
 
     def __init__(self, A: Ldu, n_coarsest=50, max_levels=50, match_rounds=16,
-                 passes=1, smoother="jacobi", gs_inner=1, coarsest="diag"):
+                 passes=1, smoother="jacobi", gs_inner=1, coarsest="diag",
+                 aggressive_from=0):
         """smoother: "jacobi" (damped Jacobi / Richardson) or "gs2" (two-stage
         Gauss-Seidel with gs_inner inner steps); coarsest: the coarsest-level
         CG preconditioner, "diag" or "dic"."""
         self.A = A
-        self._h = lib().orc_gamg_build2(*A.args(), int(n_coarsest),
+        self._h = lib().orc_gamg_build3(*A.args(), int(n_coarsest),
                                         int(max_levels), int(match_rounds),
-                                        int(passes))
+                                        int(passes), int(aggressive_from))
         rc = lib().orc_gamg_set_cycle(self._h, self.SMOOTHERS[smoother], int(gs_inner),
                                       self.COARSEST[coarsest])
         if rc != OK:

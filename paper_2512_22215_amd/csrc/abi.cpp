@@ -83,6 +83,7 @@ void check_gamg_opts(const ldu_gamg_opts &o) {
         o.n_pre < 0 || o.n_post < 0 || o.max_levels < 1 || o.max_levels > kMaxLevels ||
         o.match_rounds < 0 || (o.precision != LDU_FP64 && o.precision != LDU_MIXED) ||
         o.max_refine < 0 || !(o.omega > 0.0) || o.passes < 1 || o.passes > 3 ||
+        o.aggressive_from < 0 ||
         (o.smoother != LDU_SMOOTH_JACOBI && o.smoother != LDU_SMOOTH_GS2) ||
         o.gs_inner < 1 || o.gs_inner > 8 ||
         (o.coarsest != LDU_COARSE_DIAG && o.coarsest != LDU_COARSE_DIC) ||
@@ -92,7 +93,8 @@ void check_gamg_opts(const ldu_gamg_opts &o) {
 
 bool same_structure(const ldu_gamg_opts &a, const ldu_gamg_opts &b) {
     return a.n_coarsest == b.n_coarsest && a.max_levels == b.max_levels &&
-           a.match_rounds == b.match_rounds && a.passes == b.passes;
+           a.match_rounds == b.match_rounds && a.passes == b.passes &&
+           a.aggressive_from == b.aggressive_from;
 }
 
 void ensure_gamg(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
@@ -135,6 +137,7 @@ void ldu_gamg_default_opts(ldu_gamg_opts *o) {
     o->max_refine = 200;
     o->omega = 0.75;
     o->passes = 1;
+    o->aggressive_from = 0;
     o->smoother = LDU_SMOOTH_JACOBI;
     o->gs_inner = 1;
     o->coarsest = LDU_COARSE_DIAG;

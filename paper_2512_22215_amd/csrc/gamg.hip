@@ -422,7 +422,8 @@ void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
     while ((int)h->levels.size() < maxl) {
         const size_t l = h->levels.size() - 1;
         if (h->levels[l].n <= o.n_coarsest) break;
-        const int32_t nc = agglomerate_passes(h, h->levels[l], o.match_rounds, o.passes, ar, st);
+        const int passes = (int)l >= o.aggressive_from ? o.passes : 1;
+        const int32_t nc = agglomerate_passes(h, h->levels[l], o.match_rounds, passes, ar, st);
         if (100 * (int64_t)nc > 95 * (int64_t)h->levels[l].n) {
             h->levels[l].agg = nullptr;
             break;
@@ -431,6 +432,11 @@ void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
         galerkin(h, h->levels[l], C, ar, st);
         build_level_sell(h, ar, C, false, st);
         h->levels.push_back(C);
+    }
+    if (h->levels.back().n > kMaxCoarsest && h->levels.back().nf > 0) {
+        h->levels.clear();
+        h->gamg_arena.release_all();
+        throw Error(LDU_ERR_LIMIT, "coarsest GAMG level has more than 8192 cells; raise max_levels");
     }
     for (auto &L : h->levels) alloc_work(L, ar);
     h->coarse_work = ar.get<double>(5 * (size_t)h->levels.back().n);

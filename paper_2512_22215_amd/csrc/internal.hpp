@@ -39,6 +39,11 @@ constexpr int kMaxGrid = 2048;     // streaming kernels: at most this many block
 constexpr int kMaxLevels = 64;
 constexpr int kMaxCoarseRow = 128; // widest coarse-level row the setup supports
 constexpr double kCoarsestTol = 1e-10;
+// largest coarsest level (with off-diagonal entries) the single-workgroup CG
+// accepts: its iteration cap max(2n, 100) keeps that kernel to a fraction of
+// a second; a hierarchy cut off above it (max_levels, stalled coarsening) is
+// refused at setup
+constexpr int kMaxCoarsest = 8192;
 
 // ---------------------------------------------------------------- errors
 struct Error : std::runtime_error {

@@ -228,11 +228,14 @@ __global__ void k_slice_table(int64_t S, const int32_t *pdeg, const int32_t *tpt
     }
 }
 
-// max of a[0..n) by one block
+// max of a[0..n) (values >= 0) into *out, which the caller zeroes: one
+// partial per block, combined by an integer atomic max (order-independent)
 __global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t *a, int64_t n, int32_t *out) {
     __shared__ int32_t sm[kBlock];
     int32_t m = 0;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) m = a[i] > m ? a[i] : m;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        m = a[i] > m ? a[i] : m;
     sm[threadIdx.x] = m;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
@@ -240,7 +243,7 @@ __global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t *a, int64_t n,
             sm[threadIdx.x] = sm[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sm[0];
+    if (threadIdx.x == 0) atomicMax(out, sm[0]);
 }
 
 __global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
@@ -408,7 +411,8 @@ void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t 
     }
     {  // longest row, for kernels that stage a whole row
         int32_t *dmax = tmp.get<int32_t>(1);
-        k_max_i32<<<1, kBlock, 0, st>>>(deg, n, dmax);
+        k_fill_i32<<<1, kBlock, 0, st>>>(dmax, 1, 0);
+        k_max_i32<<<grid_for(n), kBlock, 0, st>>>(deg, n, dmax);
         HIP_CHECK(hipMemcpyAsync(&L.max_row, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipStreamSynchronize(st));
     }

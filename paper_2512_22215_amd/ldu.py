@@ -46,7 +46,8 @@ class GamgOpts(C.Structure):
                 ("n_coarsest", C.c_int), ("n_pre", C.c_int), ("n_post", C.c_int),
                 ("max_levels", C.c_int), ("scale_correction", C.c_int),
                 ("match_rounds", C.c_int), ("precision", C.c_int), ("max_refine", C.c_int),
-                ("omega", C.c_double), ("passes", C.c_int), ("smoother", C.c_int),
+                ("omega", C.c_double), ("passes", C.c_int), ("aggressive_from", C.c_int),
+                ("smoother", C.c_int),
                 ("gs_inner", C.c_int), ("coarsest", C.c_int)]
 
 

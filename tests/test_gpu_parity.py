@@ -160,14 +160,15 @@ def _gamg_case(name):
     return CASES[name]
 
 
-@pytest.mark.parametrize("name,passes", [("c2s", 1), ("c3s", 1), ("ragged", 1), ("c1", 1),
-                                         ("nonsym", 1), ("c2s", 2), ("c3s", 2), ("ragged", 3),
-                                         ("nonsym", 2)])
-def test_gamg_hierarchy_bit_exact(name, passes):
+@pytest.mark.parametrize("name,passes,afrom", [
+    ("c2s", 1, 0), ("c3s", 1, 0), ("ragged", 1, 0), ("c1", 1, 0), ("nonsym", 1, 0),
+    ("c2s", 2, 0), ("c3s", 2, 0), ("ragged", 3, 0), ("nonsym", 2, 0), ("c3s", 3, 1),
+    ("c2s", 3, 2)])
+def test_gamg_hierarchy_bit_exact(name, passes, afrom):
     c = _gamg_case(name)
     m = _lib().from_case(c)
-    m.gamg_setup(passes=passes)
-    g = O.Gamg(O.Ldu.from_case(c), passes=passes)
+    m.gamg_setup(passes=passes, aggressive_from=afrom)
+    g = O.Gamg(O.Ldu.from_case(c), passes=passes, aggressive_from=afrom)
     assert m.n_levels() == g.n_levels
     for l in range(g.n_levels):
         got = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in m.level(l).items()}
@@ -431,3 +432,17 @@ def test_autograd_matches_oracle_and_finite_differences():
         am = c.upper.copy(); am[f] -= h
         fd = (L(ap) - L(am)) / (2 * h)
         assert abs(fd - ga[f]) <= 1e-5 * max(abs(ga[f]), 1e-3 * np.abs(ga).max())
+
+
+def test_oversized_coarsest_level_is_refused_at_setup():
+    """A hierarchy cut off above 8192 coarsest cells (here by max_levels) is
+    refused before any solve; the handle stays usable."""
+    from paper_2512_22215_amd import LduError
+    from paper_2512_22215_amd.ldu import LDU_ERR_LIMIT
+    c = _gamg_case("c5s")
+    m = _lib().from_case(c)
+    with pytest.raises(LduError) as e:
+        m.gamg_setup(max_levels=2)
+    assert e.value.code == LDU_ERR_LIMIT
+    x, st = m.gamg(_t(c.rhs[0]), rel_tol=1e-8)
+    assert st.converged and true_res(c, x.cpu().numpy()) <= 1e-8

@@ -775,3 +775,22 @@ def test_gamg_variants_converge_to_dense_solution(smoother, coarsest):
     g1 = O.Gamg(A, n_coarsest=10 ** 6, coarsest=coarsest)
     e = g1.vcycle(c.rhs[0])
     assert np.linalg.norm(c.rhs[0] - O.amul(A, e)) <= 1e-10 * np.linalg.norm(c.rhs[0])
+
+
+def test_aggressive_from_keeps_pairwise_levels_above():
+    """aggressive_from = k: levels above k coarsen exactly as plain pairwise
+    agglomeration does; level k onwards uses the composed passes."""
+    c = box_case(12, 11, 10, coeff="lognormal", dirichlet_x0=1.0, seed=48)
+    A = O.Ldu.from_case(c)
+    g1 = O.Gamg(A, passes=1)
+    for k in (1, 2):
+        gk = O.Gamg(A, passes=3, aggressive_from=k)
+        for l in range(k):
+            assert np.array_equal(gk.level(l).agg, g1.level(l).agg)
+        assert gk.level(k).n == g1.level(k).n
+        # below: the composed three-pass aggregation of level k's matrix
+        Lk = gk.level(k)
+        sub = O.Gamg(O.Ldu(Lk.n, Lk.owner, Lk.neighbour, Lk.diag, Lk.upper, Lk.lower),
+                     passes=3, max_levels=2, n_coarsest=1)
+        assert np.array_equal(gk.level(k).agg, sub.level(0).agg)
+        assert gk.n_levels < g1.n_levels

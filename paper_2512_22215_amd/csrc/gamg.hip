@@ -526,11 +526,28 @@ k_vc_zero(int32_t n, int64_t S, T *__restrict__ e, const DevScalars *ds) {
 
 // e_out = e + omega (r - A e) / D; DOT also accumulates the block partials of
 // rdot . e_out (the preconditioned CG's r . z, saving a pass over both)
-template <bool CMP, bool DOT, typename T>
+// The finer level's unscaled correction e_f += P e_c, applied by the kernel
+// that produces e_c: row a adds its value to the members of aggregate a.
+template <typename T>
+struct FineCorr {
+    T *e;
+    const int32_t *start, *cells;
+    __device__ __forceinline__ void operator()(int32_t a, T v) const {
+        for (int32_t k = start[a]; k < start[a + 1]; ++k) {
+            const int32_t j = cells[k];
+            e[j] = e[j] + v;
+        }
+    }
+};
+
+// e_out = e + omega (r - A e) / D; DOT also accumulates the block partials of
+// rdot . e_out (the preconditioned CG's r . z, saving a pass over both); CORR
+// also applies the finer level's correction with e_out
+template <bool CMP, bool DOT, bool CORR, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
             T *__restrict__ eo, T omega, const T *__restrict__ rdot, double *partials,
-            const DevScalars *ds) {
+            FineCorr<T> fc, const DevScalars *ds) {
     if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
@@ -542,6 +559,7 @@ k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
             const T zi = e[i] + omega * (r[i] - y) / A.diag[i];
             eo[i] = zi;
             if constexpr (DOT) acc[0] += (double)rdot[i] * (double)zi;
+            if constexpr (CORR) fc(i, zi);
         }
     });
     if constexpr (DOT) block_partials<1>(acc, partials);
@@ -599,12 +617,15 @@ k_vc_gs(SellView<T> A, const T *__restrict__ t, const T *__restrict__ g, T *__re
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_restrict(int32_t nc, const int32_t *__restrict__ start, const int32_t *__restrict__ cells,
-              const T *__restrict__ t, T *__restrict__ rc, const DevScalars *ds) {
+              const T *__restrict__ t, T *__restrict__ rc, T *__restrict__ ec_first,
+              const T *__restrict__ Dc, T omega, const DevScalars *ds) {
     if (vc_skip(ds)) return;
     GRID_STRIDE(a, nc) {
         T s = T(0);
         for (int32_t k = start[a]; k < start[a + 1]; ++k) s += t[cells[k]];
         rc[a] = s;
+        // the coarse level's first Jacobi sweep from zero, e_c = omega r_c / D_c
+        if (ec_first) ec_first[a] = omega * s / Dc[a];
     }
 }
 
@@ -808,7 +829,8 @@ __global__ void __launch_bounds__(kWave)
 k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
                 const float *__restrict__ rhs_f, double *__restrict__ eo_d,
                 float *__restrict__ eo_f, int singular, double tol, int max_it,
-                const double *__restrict__ dt, const DevScalars *ds) {
+                const double *__restrict__ dt, FineCorr<double> fcd, FineCorr<float> fcf,
+                const DevScalars *ds) {
     __shared__ int32_t cL[kWaveRow * kWave];
     __shared__ double vL[kWaveRow * kWave];
     __shared__ double p[kWave];
@@ -898,9 +920,15 @@ k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
             pi = zi + beta * pi;
         }
     }
-    if (i < n) {
-        if (eo_d) eo_d[i] = xi;
-        else eo_f[i] = (float)xi;
+    if (i < n) {  // the result, and the finer level's correction with it
+        if (eo_d) {
+            eo_d[i] = xi;
+            if (fcd.e) fcd(i, xi);
+        } else {
+            const float v = (float)xi;
+            eo_f[i] = v;
+            if (fcf.e) fcf(i, v);
+        }
     }
 }
 
@@ -953,18 +981,28 @@ k_refine_add(int32_t n, int64_t S, const float *__restrict__ d, double *__restri
     });
 }
 
-// one Jacobi sweep; with rdot, also the block partials of rdot . e_out
+template <bool CMP, typename T>
+static void launch_jacobi_l(const SellView<T> &A, const T *r, const T *e, T *eo, T omega,
+                            const T *rdot, double *partials, const FineCorr<T> &fc,
+                            const DevScalars *ds, int G, hipStream_t st) {
+    if (rdot && fc.e)
+        k_vc_jacobi<CMP, true, true, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, fc, ds);
+    else if (rdot)
+        k_vc_jacobi<CMP, true, false, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, fc, ds);
+    else if (fc.e)
+        k_vc_jacobi<CMP, false, true, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, fc, ds);
+    else
+        k_vc_jacobi<CMP, false, false, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, fc, ds);
+}
+
+// one Jacobi sweep; with rdot, also the block partials of rdot . e_out; with
+// fc.e, also the finer level's correction
 template <typename T>
 static void launch_jacobi(const SellView<T> &A, const T *r, const T *e, T *eo, T omega,
-                          const T *rdot, double *partials, const DevScalars *ds, int G,
-                          hipStream_t st) {
-    if (A.pdeg) {
-        if (rdot) k_vc_jacobi<true, true, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, ds);
-        else k_vc_jacobi<true, false, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, ds);
-    } else {
-        if (rdot) k_vc_jacobi<false, true, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, ds);
-        else k_vc_jacobi<false, false, T><<<G, kBlock, 0, st>>>(A, r, e, eo, omega, rdot, partials, ds);
-    }
+                          const T *rdot, double *partials, const FineCorr<T> &fc,
+                          const DevScalars *ds, int G, hipStream_t st) {
+    if (A.pdeg) launch_jacobi_l<true, T>(A, r, e, eo, omega, rdot, partials, fc, ds, G, st);
+    else launch_jacobi_l<false, T>(A, r, e, eo, omega, rdot, partials, fc, ds, G, st);
 }
 
 template <bool CMP, bool UPPER, typename T>
@@ -1032,13 +1070,21 @@ float *lvec<float>(Level &L, int which) {
                                                                                      : L.w32;
 }
 
-// one V-cycle e = V(l, r); returns the buffer holding e.  With rdot, the last
-// level-l kernel also leaves the block partials of rdot . e in h->partials
-// and *dotted is set (only when that last kernel is a Jacobi sweep).
+constexpr int kFuseCorrRows = 1 << 17;
+
+// One V-cycle e = V(l, r); returns the buffer holding e.  With rdot, the
+// last level-l kernel also leaves the block partials of rdot . e in
+// h->partials and *dotted is set (only when that kernel is a Jacobi sweep).
+// e_ready: the caller's restriction already stored the first Jacobi sweep
+// e = omega r / D in this level's e.  fc: the finer level's unscaled
+// correction e_f += P e, applied here by the kernel that produces e when it
+// can (*corrected tells the caller).
 template <typename T>
 static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
-                 bool *dotted = nullptr) {
+                 bool *dotted = nullptr, bool e_ready = false, FineCorr<T> fc = {},
+                 bool *corrected = nullptr) {
     if (dotted) *dotted = false;
+    if (corrected) *corrected = false;
     ldu_t *h = c.h;
     Level &L = h->levels[l];
     hipStream_t st = c.st;
@@ -1048,10 +1094,16 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
         const size_t lds = L.n <= kLdsCoarse ? sizeof(double) * 5 * L.n : 0;
         if (L.n <= kWave && L.max_row <= kWaveRow) {
             const bool f64 = sizeof(T) == sizeof(double);
+            FineCorr<double> fcd{};
+            FineCorr<float> fcf{};
+            if (f64) fcd = {(double *)fc.e, fc.start, fc.cells};
+            else fcf = {(float *)fc.e, fc.start, fc.cells};
             k_coarsest_wave<<<1, kWave, 0, st>>>(
                 L.A.view(c.tr), f64 ? (const double *)r : nullptr,
                 f64 ? nullptr : (const float *)r, f64 ? (double *)e : nullptr,
-                f64 ? nullptr : (float *)e, L.singular, kCoarsestTol, maxit, c.dt, h->dev);
+                f64 ? nullptr : (float *)e, L.singular, kCoarsestTol, maxit, c.dt, fcd, fcf,
+                h->dev);
+            if (corrected && fc.e) *corrected = true;
         } else
             k_coarsest<T, kWavesPerBlock><<<1, kBlock, lds, st>>>(L.A.view(c.tr), r, e, c.cw,
                                                                  L.singular, kCoarsestTol,
@@ -1070,10 +1122,11 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
         for (int k = 0; k < c.o->n_pre; ++k)
             gs_sweep<T>(A, r, e, t, e2, w1, k == 0, false, c.o->gs_inner, h->dev, G, st);
     } else {
-        if (c.o->n_pre > 0) k_vc_first<T><<<G, kBlock, 0, st>>>(L.n, S, r, A.diag, e, omega, h->dev);
-        else k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
+        if (c.o->n_pre == 0) k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
+        else if (!e_ready)
+            k_vc_first<T><<<G, kBlock, 0, st>>>(L.n, S, r, A.diag, e, omega, h->dev);
         for (int k = 1; k < c.o->n_pre; ++k) {
-            launch_jacobi<T>(A, r, e, e2, omega, nullptr, nullptr, h->dev, G, st);
+            launch_jacobi<T>(A, r, e, e2, omega, nullptr, nullptr, {}, h->dev, G, st);
             std::swap(e, e2);
         }
     }
@@ -1081,23 +1134,37 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
     else k_vc_resid<false, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
     Level &C = h->levels[l + 1];
     T *rc = lvec<T>(C, 0);
-    k_vc_restrict<T><<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, t, rc, h->dev);
-    const T *ec = vcycle<T>(c, l + 1, rc);
+    // the coarse level's first Jacobi sweep rides on the restriction
+    const bool c_first = !gs && c.o->n_pre > 0 && l + 2 < h->levels.size();
+    k_vc_restrict<T><<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, t, rc,
+                                                    c_first ? lvec<T>(C, 1) : nullptr,
+                                                    lview<T>(C, c.tr).diag, omega, h->dev);
+    // without correction scaling, on levels small enough to be bound by launch
+    // latency, the coarse level applies e += P e_c itself (a scatter through
+    // the member lists: on large levels the gather form of k_vc_correct moves
+    // fewer bytes)
+    const bool fuse_corr = !c.o->scale_correction && L.n <= kFuseCorrRows;
+    bool done_corr = false;
+    const T *ec = vcycle<T>(c, l + 1, rc, nullptr, nullptr, c_first,
+                            fuse_corr ? FineCorr<T>{e, L.aggStart, L.aggCells} : FineCorr<T>{},
+                            &done_corr);
     if (c.o->scale_correction) {
         if (A.pdeg) k_vc_scale<true, T><<<G, kBlock, 0, st>>>(A, ec, L.agg, t, h->partials, h->dev);
         else k_vc_scale<false, T><<<G, kBlock, 0, st>>>(A, ec, L.agg, t, h->partials, h->dev);
         launch_finalize<2>(h->partials, G, h->dev, EpiScale{}, st);
     }
-    k_vc_correct<T><<<G, kBlock, 0, st>>>(L.n, S, ec, L.agg, e, c.o->scale_correction, h->dev);
+    if (!done_corr)
+        k_vc_correct<T><<<G, kBlock, 0, st>>>(L.n, S, ec, L.agg, e, c.o->scale_correction, h->dev);
     for (int k = 0; k < c.o->n_post; ++k) {
+        const bool last = k + 1 == c.o->n_post;
         if (gs) {  // backward sweeps: the V-cycle stays symmetric
             gs_sweep<T>(A, r, e, t, e2, w1, false, true, c.o->gs_inner, h->dev, G, st);
-        } else {  // the last sweep may also take the caller's dot product
-            const bool last = k + 1 == c.o->n_post;
-            launch_jacobi<T>(A, r, e, e2, omega, last ? rdot : nullptr, h->partials, h->dev, G,
-                             st);
+        } else {  // the last sweep may take the caller's dot product and correction
+            launch_jacobi<T>(A, r, e, e2, omega, last ? rdot : nullptr, h->partials,
+                             last ? fc : FineCorr<T>{}, h->dev, G, st);
             std::swap(e, e2);
             if (last && rdot && dotted) *dotted = true;
+            if (last && fc.e && corrected) *corrected = true;
         }
     }
     HIP_CHECK(hipGetLastError());

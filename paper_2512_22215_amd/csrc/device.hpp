@@ -151,23 +151,24 @@ __device__ __forceinline__ T sell_row(const SellView<T> &A, int64_t s, int lane,
     } else {
         w = (int)((A.sptr[s + 1] - b0) >> 6);
     }
-    for (int k = 0; k < w; k += 8) {
-        int32_t c[8];
-        T v[8];
+    constexpr int B = CMP ? kCmpBatch : 8;  // entries loaded per batch
+    for (int k = 0; k < w; k += B) {
+        int32_t c[B];
+        T v[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < B; ++u) {
             if (k + u < w) {
                 const int64_t o = CMP ? (int64_t)ot[k + u] : (int64_t)(k + u) * kWave;
                 c[u] = __builtin_nontemporal_load(cp + o);
                 v[u] = __builtin_nontemporal_load(vp + o);
             }
         }
-        T xv[8];
+        T xv[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < B; ++u)
             if (k + u < w) xv[u] = xa(c[u]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < B; ++u)
             if (k + u < w) acc = acc + v[u] * xv[u];
     }
     return acc;

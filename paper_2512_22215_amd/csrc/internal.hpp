@@ -36,6 +36,10 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxGrid = 2048;     // streaming kernels: at most this many blocks
+#ifndef LDU_CMP_BATCH
+#define LDU_CMP_BATCH 16
+#endif
+constexpr int kCmpBatch = LDU_CMP_BATCH;  // compressed-slice row products: entries per batch
 constexpr int kMaxLevels = 64;
 constexpr int kMaxCoarseRow = 128; // widest coarse-level row the setup supports
 constexpr double kCoarsestTol = 1e-10;

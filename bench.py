@@ -198,7 +198,7 @@ def main():
     assert st.converged and res <= 1e-8, (st, res)
     t_step = float(np.mean(times))
 
-    variants, mixed_rec, adj_rec = {}, None, None
+    variants, mixed_rec, adj_rec, bicg_rec = {}, None, None, None
     if not args.no_extra:
         # the mixed form of the same solve: FP64 refinement around FP32 CG with an
         # FP32 V-cycle preconditioner (one warm-up, then the same step count)
@@ -273,7 +273,29 @@ def main():
                 f"({rec['fp64']['iterations']} it), mixed {rec['mixed']['s']:.4f} s")
         m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
 
+        # the non-symmetric solve (PBiCG, diagonal preconditioner) on the
+        # convection-diffusion box of the same size (200^3, upwind, Courant 2)
+        cu = config_case("c5u", n=args.n)
+        mu = LduMatrix.from_case(cu)
+        bu = torch.from_numpy(cu.rhs[0]).to(dev)
+        mu.pbicg(bu, rel_tol=1e-8, max_iter=5000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xu, su = mu.pbicg(bu, rel_tol=1e-8, max_iter=5000)
+        torch.cuda.synchronize()
+        t_bicg = time.perf_counter() - t0
+        ures = mu.residual(bu, xu)
+        assert su.converged and ures <= 1e-8, (su, ures)
+        log(f"[bench] PBiCG on the {args.n}^3 convection-diffusion box: {t_bicg:.4f} s, "
+            f"{su.iterations} iterations")
+        bicg_rec = {"s": t_bicg, "iterations": su.iterations, "true_residual": ures,
+                    "workload": f"c5u: {args.n}^3 upwind convection-diffusion, {cu.n_cells} cells",
+                    "ms_per_iteration": t_bicg / max(su.iterations, 1) * 1e3}
+        mu.close()
+        del mu, xu, bu
+
     extra = {
+        "pbicg_nonsymmetric": bicg_rec,
         "variants": variants,
         "adjoint": adj_rec,
         "mixed_solve": mixed_rec,

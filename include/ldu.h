@@ -184,6 +184,16 @@ int ldu_residual(ldu_handle h, const double *b, const double *x, double *out,
 int pcg_solve(ldu_handle h, const double *b, double *x,
               const ldu_pcg_opts *opts, ldu_stats *stats, void *hip_stream);
 
+/* PBiCG for non-symmetric A (the paper's solver for the velocity and
+ * turbulence systems, Appendix A): preconditioned bi-conjugate gradients with
+ * the shadow residual equal to the residual at each (re)start, one fused
+ * Amul + Tmul pass per iteration.  opts->precond 0 (none) or 1 (diagonal);
+ * precision must be LDU_FP64.  x holds x0 on entry.  The first call on a
+ * handle allocates its three shadow vectors.  LDU_ERR_BREAKDOWN when
+ * |pt.A p| or |(M^-1 r).rt| falls to 1e-300. */
+int pbicg_solve(ldu_handle h, const double *b, double *x,
+                const ldu_pcg_opts *opts, ldu_stats *stats, void *hip_stream);
+
 /* Build the GAMG hierarchy (agglomeration + Galerkin coarse matrices); done
  * lazily by gamg_solve otherwise.  Calling it again rebuilds. */
 int gamg_setup(ldu_handle h, const ldu_gamg_opts *opts, void *hip_stream);
@@ -208,11 +218,13 @@ int gamg_level_export(ldu_handle h, int level, int32_t *agg, int32_t *owner,
                       int32_t *neighbour, double *diag, double *upper,
                       double *lower, void *hip_stream);
 
-/* Adjoint solve A^T lambda = g with PCG (use_gamg = 0, opts is an
- * ldu_pcg_opts*) or GAMG (use_gamg = 1, opts is an ldu_gamg_opts*), on the
- * transposed coefficients (upper and lower exchanged on every level). */
+/* Adjoint solve A^T lambda = g on the transposed coefficients (upper and
+ * lower exchanged on every level) with solver 0: PCG (opts is an
+ * ldu_pcg_opts*), 1: GAMG (an ldu_gamg_opts*), or 2: PBiCG (an
+ * ldu_pcg_opts*; for non-symmetric A). */
+enum { LDU_SOLVER_PCG = 0, LDU_SOLVER_GAMG = 1, LDU_SOLVER_PBICG = 2 };
 int ldu_adjoint_solve(ldu_handle h, const double *g, double *lambda,
-                      int use_gamg, const void *opts, ldu_stats *stats,
+                      int solver, const void *opts, ldu_stats *stats,
                       void *hip_stream);
 
 /* Gradients of a loss L through A x = b given lambda = A^-T dL/dx:

@@ -331,6 +331,42 @@ def config_c5(n=100) -> LduCase:
                     "a_boundary": ab})
 
 
+def config_c5u(n=100, velocity=(1.0, 0.5, 0.25), courant=2.0) -> LduCase:
+    """Non-symmetric stand-in for the velocity / turbulence systems the paper
+    solves with PBiCG: one implicit Euler step of u_t + div(U u) =
+    div(nu grad u) on the c5 box (h = 1/n), finite volumes with upwind
+    convection.  Per face f (owner -> neighbour along axis k): diffusion
+    D_f = nu_f h with nu_f = exp(0.5 N(0,1)) / n (seed s = 2, as c5), flux
+    F_f = U_k h^2 >= 0; upper_f = -D_f, lower_f = -(D_f + F_f).  The diagonal
+    holds each cell's outflow coefficients (D_f + F_f for the owner, D_f for
+    the neighbour), h^3 / dt with dt = courant h / |U|, the upwind outflow
+    U_k h^2 on the boundary faces at the far end of each axis, and a
+    Dirichlet diffusion coefficient 2 mean(nu) h on the x = 0 inflow face.
+    Column sums are non-negative: an M-matrix.  rhs N(0,1) (s = 3)."""
+    own, nb, ax = box_faces(n, n, n)
+    N = n ** 3
+    h = 1.0 / n
+    nu = np.exp(0.5 * _rng(5, 2).standard_normal(own.size)) / n
+    U = np.asarray(velocity, dtype=np.float64)
+    D = nu * h
+    F = U[ax] * h * h
+    up = -D
+    lo = -(D + F)
+    dt = courant * h / np.linalg.norm(U)
+    diag = np.full(N, h ** 3 / dt)
+    # outflow from the owner through f is D + F, from the neighbour D
+    np.add.at(diag, own, D + F)
+    np.add.at(diag, nb, D)
+    i = np.arange(N)
+    ijk = (i % n, (i // n) % n, i // (n * n))
+    for k in range(3):
+        diag[ijk[k] == n - 1] += U[k] * h * h
+    diag[ijk[0] == 0] += 2.0 * nu.mean() * h
+    b = _rng(5, 3).standard_normal(N)
+    return LduCase("c5u", N, own, nb, diag, up, lo, [b], False,
+                   {"shape": (n, n, n), "velocity": tuple(U), "courant": courant})
+
+
 def config_case(name: str, **kw) -> LduCase:
     return {"c1": config_c1, "c2": config_c2, "c3": config_c3,
-            "c4": config_c4, "c5": config_c5}[name](**kw)
+            "c4": config_c4, "c5": config_c5, "c5u": config_c5u}[name](**kw)

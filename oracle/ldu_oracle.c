@@ -251,6 +251,107 @@ int orc_pcg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
 }
 
 /* ------------------------------------------------------------------------ */
+/* PBiCG: preconditioned bi-conjugate gradients for non-symmetric A, the     */
+/* paper's solver for the U, k and omega systems (Appendix A solver tables), */
+/* which is why its profile lists Amul + Tmul together (Sec. 4.3).  Textbook */
+/* form (Fletcher 1976; Saad, Alg. 7.3 with a preconditioner), shadow        */
+/* residual taken equal to the initial residual:                              */
+/*   r = b - A x; rt = r; z = M^-1 r; zt = M^-T rt; p = z; pt = zt;           */
+/*   rho = z.rt                                                               */
+/*   repeat: q = A p; qt = A^T pt; sigma = pt.q; alpha = rho/sigma;           */
+/*           x += alpha p; r -= alpha q; rt -= alpha qt;                      */
+/*           stop if ||r||/||b|| <= tol;                                      */
+/*           z = M^-1 r; zt = M^-T rt; rho' = z.rt; beta = rho'/rho;          */
+/*           p = z + beta p; pt = zt + beta pt                                */
+/* M is the diagonal (M^-T = M^-1) or the identity.  Breakdown when |sigma|  */
+/* or |rho'| <= 1e-300 or either is not finite.  On exit the true residual   */
+/* is recomputed, and the iteration restarts from it (with a new shadow      */
+/* residual) while it is above tol and iterations remain.                    */
+/* Pins: dense non-symmetric solves; on symmetric A it reproduces PCG.       */
+/* ------------------------------------------------------------------------ */
+
+static void apply_diag(const omat *m, int precond, const double *r, double *z) {
+    for (int32_t i = 0; i < m->n; ++i) z[i] = precond ? r[i] / m->diag[i] : r[i];
+}
+
+/* y = A^T x for the matrix view m */
+static void mat_mul_t(const omat *m, const double *x, double *y) {
+    orc_amul(m->n, m->nf, m->own, m->nb, m->diag, m->lo, m->up, x, y);
+}
+
+int orc_pbicg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+              const double *diag, const double *upper, const double *lower,
+              const double *b, double *x, double tol, int max_iter, int precond,
+              int transpose, int *iters, double *hist, double *true_res) {
+    omat m = make_mat(n, nf, own, nb, diag, upper, lower, transpose);
+    int total = 0;
+    if (iters) *iters = 0;
+    double bnorm = sqrt(dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        if (hist) hist[0] = 0.0;
+        if (true_res) *true_res = 0.0;
+        return ORC_OK;
+    }
+    double *r = xcalloc((size_t)n + 1, sizeof(double));
+    double *rt = xcalloc((size_t)n + 1, sizeof(double));
+    double *z = xcalloc((size_t)n + 1, sizeof(double));
+    double *zt = xcalloc((size_t)n + 1, sizeof(double));
+    double *p = xcalloc((size_t)n + 1, sizeof(double));
+    double *pt = xcalloc((size_t)n + 1, sizeof(double));
+    double *q = xcalloc((size_t)n + 1, sizeof(double));
+    double *qt = xcalloc((size_t)n + 1, sizeof(double));
+    residual(&m, b, x, r);
+    double res = sqrt(dot(n, r, r)) / bnorm;
+    if (hist) hist[0] = res;
+    int st = ORC_OK;
+    if (!isfinite(res)) st = ORC_ERR_NAN;
+    while (st == ORC_OK && res > tol) {
+        /* (re)start from the current residual with the shadow rt = r */
+        int run = ORC_NOT_CONVERGED;
+        memcpy(rt, r, (size_t)n * sizeof(double));
+        apply_diag(&m, precond, r, z);
+        apply_diag(&m, precond, rt, zt);
+        memcpy(p, z, (size_t)n * sizeof(double));
+        memcpy(pt, zt, (size_t)n * sizeof(double));
+        double rho = dot(n, z, rt);
+        while (total < max_iter) {
+            mat_mul(&m, p, q);
+            mat_mul_t(&m, pt, qt);
+            double sigma = dot(n, pt, q);
+            if (!isfinite(sigma) || fabs(sigma) <= 1e-300) { run = ORC_ERR_BREAKDOWN; break; }
+            double alpha = rho / sigma;
+            for (int32_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+            for (int32_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+            for (int32_t i = 0; i < n; ++i) rt[i] = rt[i] - alpha * qt[i];
+            total += 1;
+            double rr = sqrt(dot(n, r, r)) / bnorm;
+            if (hist) hist[total] = rr;
+            if (!isfinite(rr)) { run = ORC_ERR_NAN; break; }
+            if (rr <= tol) { run = ORC_OK; break; }
+            apply_diag(&m, precond, r, z);
+            apply_diag(&m, precond, rt, zt);
+            double rho_new = dot(n, z, rt);
+            if (!isfinite(rho_new) || fabs(rho_new) <= 1e-300) { run = ORC_ERR_BREAKDOWN; break; }
+            double beta = rho_new / rho;
+            rho = rho_new;
+            for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+            for (int32_t i = 0; i < n; ++i) pt[i] = zt[i] + beta * pt[i];
+        }
+        if (run < 0) { st = run; break; }
+        residual(&m, b, x, r); /* true residual, restart point */
+        res = sqrt(dot(n, r, r)) / bnorm;
+        if (!isfinite(res)) { st = ORC_ERR_NAN; break; }
+        if (res <= tol) break;
+        if (total >= max_iter) { st = ORC_NOT_CONVERGED; break; }
+    }
+    if (iters) *iters = total;
+    if (true_res) *true_res = res;
+    free(r); free(rt); free(z); free(zt); free(p); free(pt); free(q); free(qt);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Mixed precision: FP32 inner CG inside FP64 iterative refinement.          */
 /* Not in the paper (a precision variant of its PCG).  Outer loop:           */
 /*   r = b - A64 x (FP64); while ||r||/||b|| > tol:                           */

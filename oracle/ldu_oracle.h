@@ -62,6 +62,13 @@ int orc_pcg_mixed(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
                   int *refinements, int *inner_iters, double *hist,
                   double *true_res);
 
+/* PBiCG (non-symmetric A): precond 0 none, 1 diagonal; transpose solves
+ * A^T x = b */
+int orc_pbicg(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+              const double *diag, const double *upper, const double *lower,
+              const double *b, double *x, double tol, int max_iter, int precond,
+              int transpose, int *iters, double *hist, double *true_res);
+
 /* ---- GAMG: pairwise agglomeration hierarchy, V-cycle, solve ---- */
 typedef struct orc_gamg orc_gamg;
 

@@ -69,6 +69,7 @@ def lib():
     L.orc_amul_f32.argtypes = [i32, i64, _i32p, _i32p, _f32p, _f32p, _f32p, _f32p, _f32p]
     L.orc_pcg.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p,
                           d, C.c_int, C.c_int, C.c_int, ip, _f64o, dp]
+    L.orc_pbicg.argtypes = L.orc_pcg.argtypes
     L.orc_pcg_mixed.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p,
                                 _f64p, d, C.c_int, d, C.c_int, C.c_int, ip, ip, _f64o, dp]
     L.orc_gamg_build.restype = vp
@@ -179,6 +180,19 @@ def pcg(A: Ldu, b, x0=None, tol=1e-8, max_iter=10000, precond=True,
     st = lib().orc_pcg(*A.args(), _c(b, np.float64), x, float(tol),
                        int(max_iter), int(bool(precond)), int(bool(transpose)),
                        C.byref(it), hist, C.byref(tr))
+    return SolveResult(st, x, it.value, hist[: it.value + 1].copy(), tr.value)
+
+
+def pbicg(A: Ldu, b, x0=None, tol=1e-8, max_iter=10000, precond=True,
+          transpose=False):
+    """Preconditioned bi-conjugate gradients (non-symmetric A)."""
+    x = np.zeros(A.n) if x0 is None else _c(x0, np.float64).copy()
+    hist = np.zeros(max_iter + 2)
+    it = C.c_int(0)
+    tr = C.c_double(0.0)
+    st = lib().orc_pbicg(*A.args(), _c(b, np.float64), x, float(tol),
+                         int(max_iter), int(bool(precond)), int(bool(transpose)),
+                         C.byref(it), hist, C.byref(tr))
     return SolveResult(st, x, it.value, hist[: it.value + 1].copy(), tr.value)
 
 

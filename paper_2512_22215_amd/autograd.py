@@ -16,15 +16,16 @@ class LduSolve(torch.autograd.Function):
     """LduSolve.apply(diag, upper, lower, b, matrix, method, opts) -> x.
 
     matrix: an LduMatrix holding the addressing; its coefficients are replaced
-    by (diag, upper, lower) before the forward solve.  method: "pcg" or
-    "gamg"; opts: dict of solver options used for both solves.
+    by (diag, upper, lower) before the forward solve.  method: "pcg", "gamg"
+    or "pbicg" (non-symmetric A); opts: dict of solver options used for both
+    solves.
     """
 
     @staticmethod
     def forward(ctx, diag, upper, lower, b, matrix: LduMatrix, method="pcg", opts=None):
         opts = dict(opts or {})
         matrix.set_coeffs(diag.detach(), upper.detach(), lower.detach())
-        solve = matrix.gamg if method == "gamg" else matrix.pcg
+        solve = {"gamg": matrix.gamg, "pbicg": matrix.pbicg, "pcg": matrix.pcg}[method]
         x, st = solve(b.detach(), **opts)
         ctx.matrix, ctx.method, ctx.opts = matrix, method, opts
         ctx.save_for_backward(x)
@@ -35,8 +36,8 @@ class LduSolve(torch.autograd.Function):
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
         m = ctx.matrix
-        lam, _ = m.adjoint(gx.detach().to(torch.float64).contiguous(),
-                           use_gamg=(ctx.method == "gamg"), **ctx.opts)
+        lam, _ = m.adjoint(gx.detach().to(torch.float64).contiguous(), solver=ctx.method,
+                           **ctx.opts)
         gd, gu, gl = m.coeff_grad(lam, x)
         return gd, gu, gl, lam, None, None, None
 

@@ -375,13 +375,40 @@ int gamg_level_export(ldu_handle h, int level, int32_t *agg, int32_t *owner, int
     });
 }
 
-int ldu_adjoint_solve(ldu_handle h, const double *g, double *lambda, int use_gamg,
+static int pbicg_common(ldu_handle h, const double *b, double *x, const ldu_pcg_opts *opts,
+                        ldu_stats *stats, void *hip_stream, bool tr) {
+    if (!h || !b || !x) return fail(LDU_ERR_ARG, "NULL argument");
+    return guarded(h, [&] {
+        ldu_pcg_opts o;
+        ldu_pcg_default_opts(&o);
+        if (opts) o = *opts;
+        check_pcg_opts(o);
+        if (o.precond > 1 || o.precision != LDU_FP64)
+            throw Error(LDU_ERR_ARG, "PBiCG takes precond 0 or 1 and precision LDU_FP64");
+        return pbicg_fp64(h, b, x, o, tr, stats, S(hip_stream));
+    });
+}
+
+int pbicg_solve(ldu_handle h, const double *b, double *x, const ldu_pcg_opts *opts,
+                ldu_stats *stats, void *hip_stream) {
+    return pbicg_common(h, b, x, opts, stats, hip_stream, false);
+}
+
+int ldu_adjoint_solve(ldu_handle h, const double *g, double *lambda, int solver,
                       const void *opts, ldu_stats *stats, void *hip_stream) {
-    if (use_gamg)
+    switch (solver) {
+    case LDU_SOLVER_PCG:
+        return pcg_common(h, g, lambda, static_cast<const ldu_pcg_opts *>(opts), stats,
+                          hip_stream, true);
+    case LDU_SOLVER_GAMG:
         return gamg_common(h, g, lambda, static_cast<const ldu_gamg_opts *>(opts), stats,
                            hip_stream, true);
-    return pcg_common(h, g, lambda, static_cast<const ldu_pcg_opts *>(opts), stats, hip_stream,
-                      true);
+    case LDU_SOLVER_PBICG:
+        return pbicg_common(h, g, lambda, static_cast<const ldu_pcg_opts *>(opts), stats,
+                            hip_stream, true);
+    default:
+        return fail(LDU_ERR_ARG, "unknown solver");
+    }
 }
 
 int ldu_coeff_grad(ldu_handle h, const double *lambda, const double *x, double *g_diag,

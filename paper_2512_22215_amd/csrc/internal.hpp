@@ -171,6 +171,7 @@ struct ldu_t {
     bool f32_ready = false;          // FP32 copies of level values exist
     // solver buffers
     double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
+    double *rt = nullptr, *pt = nullptr, *qt = nullptr;  // PBiCG shadow vectors
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
     double *partials = nullptr;      // [4 * kMaxGrid]
     ldu::DevScalars *dev = nullptr;
@@ -217,6 +218,8 @@ double residual_norm(ldu_t *h, const Level &L, bool tr, const double *b,
                      const double *x, double *r_out, hipStream_t st);
 int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o,
              bool tr, ldu_stats *stats, hipStream_t st);
+int pbicg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
+               ldu_stats *stats, hipStream_t st);
 int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o,
               bool tr, ldu_stats *stats, hipStream_t st);
 void ensure_hist(ldu_t *h, int entries);

@@ -394,6 +394,208 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
     return status;
 }
 
+// ---------------------------------------------------------------- PBiCG
+// Preconditioned bi-conjugate gradients for non-symmetric A (the paper's
+// solver for the velocity and turbulence systems, whose profile pairs Amul
+// with Tmul).  Shadow residual rt = r at every (re)start; M = D or I.
+//   q = A p, qt = A^T pt, sigma = pt.q;  alpha = rho / sigma
+//   x += alpha p; r -= alpha q; rt -= alpha qt;  ||r||^2, rho' = (M^-1 r).rt
+//   beta = rho' / rho;  p = M^-1 r + beta p;  pt = M^-1 rt + beta pt
+
+// rt = r, pt = p (the residual kernel has set r, p = M^-1 r and rho = r.p)
+__global__ void __launch_bounds__(kBlock)
+k_bicg_start(int32_t n, int64_t S, const double *__restrict__ r, const double *__restrict__ p,
+             double *__restrict__ rt, double *__restrict__ pt, const DevScalars *ds) {
+    if (ds->done) return;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            rt[i] = r[i];
+            pt[i] = p[i];
+        }
+    });
+}
+
+// q = A p and qt = A^T pt in one pass over the shared column structure
+// (valT holds A^T at the same positions); sigma = pt . q
+template <bool CMP>
+__global__ void __launch_bounds__(kBlock)
+k_bicg_q(SellView<double> A, const double *__restrict__ valT, const double *__restrict__ p,
+         const double *__restrict__ pt, double *__restrict__ q, double *__restrict__ qt,
+         double *partials, const DevScalars *ds) {
+    if (ds->done) return;
+    SellView<double> At = A;
+    At.val = valT;
+    const int lane = threadIdx.x & 63;
+    double acc[1] = {0.0};
+    for_each_slice(A.nslices, [&](int64_t s) {
+        const int64_t pos = s * kWave + lane;
+        if (pos < A.n) {
+            const int32_t i = sv_row<CMP>(A, pos);
+            const double qi = sell_row<CMP>(A, s, lane, i, Direct<double>{p});
+            const double qti = sell_row<CMP>(At, s, lane, i, Direct<double>{pt});
+            q[i] = qi;
+            qt[i] = qti;
+            acc[0] += pt[i] * qi;
+        }
+    });
+    block_partials<1>(acc, partials);
+}
+
+// x += alpha p; r -= alpha q; rt -= alpha qt; ||r||^2 and (M^-1 r) . rt
+__global__ void __launch_bounds__(kBlock)
+k_bicg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restrict__ x,
+              double *__restrict__ r, double *__restrict__ rt, const double *__restrict__ p,
+              const double *__restrict__ q, const double *__restrict__ qt, int precond,
+              double *partials, const DevScalars *ds) {
+    if (ds->done) return;
+    const double alpha = ds->alpha;
+    const int lane = threadIdx.x & 63;
+    double acc[2] = {0.0, 0.0};
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            x[i] = x[i] + alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            const double rti = rt[i] - alpha * qt[i];
+            r[i] = ri;
+            rt[i] = rti;
+            const double zi = precond ? ri / D[i] : ri;
+            acc[0] += ri * ri;
+            acc[1] += zi * rti;
+        }
+    });
+    block_partials<2>(acc, partials);
+}
+
+// convergence as for CG, then beta, with breakdown when rho' vanishes
+struct EpiBicg {
+    double *hist;
+    __device__ bool active(const DevScalars *ds) const { return !ds->done; }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
+        const int it = ds->iters + 1;
+        ds->iters = it;
+        ds->rr = t[0];
+        const double res = sqrt(t[0]) / ds->bnorm;
+        ds->res = res;
+        if (hist) hist[it] = res;
+        if (!isfinite(res)) {
+            ds->status = LDU_ERR_NAN;
+            ds->done = kFailed;
+        } else if (res <= ds->tol) {
+            ds->done = kConverged;
+        } else if (it >= ds->max_iter) {
+            ds->done = kMaxIter;
+        } else if (!isfinite(t[1]) || fabs(t[1]) <= 1e-300) {
+            ds->status = LDU_ERR_BREAKDOWN;
+            ds->done = kFailed;
+        } else {
+            ds->beta = t[1] / ds->rho;
+            ds->rho = t[1];
+        }
+    }
+};
+
+// p = M^-1 r + beta p; pt = M^-1 rt + beta pt
+__global__ void __launch_bounds__(kBlock)
+k_bicg_p(int32_t n, int64_t S, const double *__restrict__ D, const double *__restrict__ r,
+         const double *__restrict__ rt, double *__restrict__ p, double *__restrict__ pt,
+         int precond, const DevScalars *ds) {
+    if (ds->done) return;
+    const double beta = ds->beta;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) {
+            const double zi = precond ? r[i] / D[i] : r[i];
+            const double zti = precond ? rt[i] / D[i] : rt[i];
+            p[i] = zi + beta * p[i];
+            pt[i] = zti + beta * pt[i];
+        }
+    });
+}
+
+int pbicg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
+               ldu_stats *stats, hipStream_t st) {
+    const Level &L = h->L0;
+    const SellView<double> A = L.A.view(tr);
+    const double *valT = tr ? L.A.val : L.A.valT;
+    const int n = L.n;
+    const int64_t S = L.A.nslices;
+    const int G = stream_grid_slices(S);
+    const int precond = o.precond ? 1 : 0;
+    if (!h->rt) {  // shadow vectors, allocated on the handle's first PBiCG solve
+        h->rt = h->arena.get<double>(n);
+        h->pt = h->arena.get<double>(n);
+        h->qt = h->arena.get<double>(n);
+    }
+    ensure_hist(h, o.max_iter + 2);
+    fill_stats_common(stats);
+    set_scalars_for_solve(h, o.rel_tol, o.max_iter, st);
+    launch_residual<true, false>(h, A, b, x, h->r, h->p, precond, kResPlain, true, st);
+    read_scalars(h, st);
+    DevScalars &hs = *h->host;
+    if (stats) stats->initial_residual = hs.res;
+    if (hs.bnorm == 0.0) {
+        fill(x, n, 0.0, st);
+        HIP_CHECK(hipStreamSynchronize(st));
+        if (stats) {
+            stats->iterations = 0;
+            stats->converged = 1;
+            stats->initial_residual = stats->final_residual = 0.0;
+        }
+        copy_history(h, stats, 1, st);
+        return LDU_OK;
+    }
+    if (!std::isfinite(hs.res)) throw Error(LDU_ERR_NAN, "non-finite initial residual");
+    double res = hs.res;
+    int status = LDU_OK;
+    const int every = o.check_every > 0 ? o.check_every : 16;
+    while (res > o.rel_tol) {
+        k_bicg_start<<<G, kBlock, 0, st>>>(n, S, h->r, h->p, h->rt, h->pt, h->dev);
+        for (;;) {
+            for (int k = 0; k < every; ++k) {
+                if (A.pdeg)
+                    k_bicg_q<true><<<G, kBlock, 0, st>>>(A, valT, h->p, h->pt, h->q, h->qt,
+                                                         h->partials, h->dev);
+                else
+                    k_bicg_q<false><<<G, kBlock, 0, st>>>(A, valT, h->p, h->pt, h->q, h->qt,
+                                                          h->partials, h->dev);
+                launch_finalize<1>(h->partials, G, h->dev, EpiAlpha{}, st);
+                k_bicg_update<<<G, kBlock, 0, st>>>(n, S, A.diag, x, h->r, h->rt, h->p, h->q,
+                                                    h->qt, precond, h->partials, h->dev);
+                launch_finalize<2>(h->partials, G, h->dev, EpiBicg{h->hist}, st);
+                k_bicg_p<<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->rt, h->p, h->pt, precond,
+                                               h->dev);
+            }
+            HIP_CHECK(hipGetLastError());
+            read_scalars(h, st);
+            if (hs.done != kRunning) break;
+        }
+        if (hs.done == kFailed) {
+            status = hs.status;
+            break;
+        }
+        // true residual; restart from it (new shadow) if the recursive one drifted
+        launch_residual<true, false>(h, A, b, x, h->r, h->p, precond, kResPlain, false, st);
+        read_scalars(h, st);
+        res = hs.res;
+        if (!std::isfinite(res)) { status = LDU_ERR_NAN; break; }
+        if (res <= o.rel_tol) { status = LDU_OK; break; }
+        if (hs.iters >= o.max_iter) { status = LDU_NOT_CONVERGED; break; }
+        k_set_done<<<1, 1, 0, st>>>(h->dev, kRunning);
+    }
+    const int iters = hs.iters;
+    if (stats) {
+        stats->iterations = iters;
+        stats->final_residual = res;
+        stats->converged = (status == LDU_OK);
+    }
+    copy_history(h, stats, iters + 1, st);
+    return status;
+}
+
 // ---------------------------------------------------------------- PCG, mixed
 // Outer FP64 refinement with inner FP32 CG.  Inner dot products accumulate
 // in FP64; alpha and beta are formed in FP64 and rounded to FP32.

@@ -19,11 +19,12 @@ LDU_OK, LDU_NOT_CONVERGED = 0, 1
 LDU_ERR_ARG, LDU_ERR_ADDR, LDU_ERR_NAN, LDU_ERR_BREAKDOWN = -1, -2, -3, -4
 LDU_ERR_NOMEM, LDU_ERR_HIP, LDU_ERR_STATE, LDU_ERR_LIMIT = -5, -6, -7, -8
 LDU_FP64, LDU_MIXED = 0, 1
+SOLVERS = {"pcg": 0, "gamg": 1, "pbicg": 2}
 
 EXPORTED = (
     "ldu_pcg_default_opts", "ldu_gamg_default_opts", "ldu_create", "ldu_set_coeffs",
     "ldu_destroy", "ldu_amul", "ldu_tmul", "ldu_amul_f32", "ldu_residual", "pcg_solve",
-    "gamg_setup", "gamg_solve", "gamg_vcycle", "gamg_level_size", "gamg_level_export",
+    "pbicg_solve", "gamg_setup", "gamg_solve", "gamg_vcycle", "gamg_level_size", "gamg_level_export",
     "ldu_adjoint_solve", "ldu_coeff_grad", "ldu_last_error",
 )
 
@@ -95,6 +96,7 @@ def lib():
         f.argtypes = [vp, vp, vp, vp]
     L.ldu_residual.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
     L.pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(Stats), vp]
+    L.pbicg_solve.argtypes = L.pcg_solve.argtypes
     L.gamg_setup.argtypes = [vp, C.POINTER(GamgOpts), vp]
     L.gamg_solve.argtypes = [vp, vp, vp, C.POINTER(GamgOpts), C.POINTER(Stats), vp]
     L.gamg_vcycle.argtypes = [vp, vp, vp, C.POINTER(GamgOpts), vp]
@@ -253,6 +255,10 @@ class LduMatrix:
     def gamg(self, b, x0=None, history=0, **kw):
         return self._solve(lib().gamg_solve, b, x0, gamg_opts(**kw), history)
 
+    def pbicg(self, b, x0=None, history=0, **kw):
+        """Preconditioned bi-conjugate gradients (non-symmetric A)."""
+        return self._solve(lib().pbicg_solve, b, x0, pcg_opts(**kw), history)
+
     def gamg_setup(self, **kw):
         o = gamg_opts(**kw)
         _check(lib().gamg_setup(self._h, C.byref(o), _stream()), False)
@@ -290,17 +296,20 @@ class LduMatrix:
                False)
         return out
 
-    def adjoint(self, g, use_gamg=False, x0=None, history=0, **kw):
+    def adjoint(self, g, use_gamg=False, x0=None, history=0, solver=None, **kw):
+        """A^T lambda = g; solver "pcg" (default), "gamg" (or use_gamg=True) or
+        "pbicg"."""
         g = self._vec(g)
         lam = torch.zeros_like(g) if x0 is None else self._vec(x0).clone()
-        opts = gamg_opts(**kw) if use_gamg else pcg_opts(**kw)
+        solver = solver or ("gamg" if use_gamg else "pcg")
+        opts = gamg_opts(**kw) if solver == "gamg" else pcg_opts(**kw)
         st = Stats()
         buf = None
         if history:
             buf = (C.c_double * history)()
             st.history = C.cast(buf, C.POINTER(C.c_double))
             st.history_len = history
-        rc = lib().ldu_adjoint_solve(self._h, _ptr(g), _ptr(lam), int(bool(use_gamg)),
+        rc = lib().ldu_adjoint_solve(self._h, _ptr(g), _ptr(lam), SOLVERS[solver],
                                      C.cast(C.pointer(opts), C.c_void_p), C.byref(st),
                                      _stream())
         _check(rc)

@@ -446,3 +446,80 @@ def test_oversized_coarsest_level_is_refused_at_setup():
     assert e.value.code == LDU_ERR_LIMIT
     x, st = m.gamg(_t(c.rhs[0]), rel_tol=1e-8)
     assert st.converged and true_res(c, x.cpu().numpy()) <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["nonsym", "c5u"])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_pbicg_matches_oracle(name, precond):
+    """PBiCG (fused Amul + Tmul) against the oracle: forward and transposed
+    solves.  The products are bit-exact and only the dot products' summation
+    orders differ, so the first ten residuals agree to 1e-8; later, BiCG's
+    near-breakdowns (it minimises nothing) amplify those roundings, so the
+    paths are compared by iteration count (within 10%) and by the solutions
+    (both at the tolerance, and within 1e-8 of each other)."""
+    from meshgen import config_case
+    c = CASES["nonsym"] if name == "nonsym" else config_case("c5u", n=24)
+    A = O.Ldu.from_case(c)
+    m = _lib().from_case(c)
+    for tr in (False, True):
+        if tr:
+            lam, st = m.adjoint(_t(c.rhs[0]), solver="pbicg", rel_tol=1e-10, precond=precond,
+                                history=2000)
+            xg = lam.cpu().numpy()
+        else:
+            x, st = m.pbicg(_t(c.rhs[0]), rel_tol=1e-10, precond=precond, history=2000)
+            xg = x.cpu().numpy()
+        ref = O.pbicg(A, c.rhs[0], tol=1e-10, precond=bool(precond), transpose=tr)
+        assert ref.status == O.OK and st.converged
+        assert abs(st.iterations - ref.iterations) <= max(1, ref.iterations // 10), \
+            (st.iterations, ref.iterations)
+        h = np.asarray(st.history)
+        dev = np.abs(h[:11] - ref.history[:11]) / ref.history[:11]
+        print(f"{name} precond {precond} transpose {tr}: {st.iterations} vs "
+              f"{ref.iterations} iterations, history deviation over 10 steps {dev.max():.2e}")
+        assert dev.max() <= 1e-8
+        bt = O.tmul(A, xg) if tr else O.amul(A, xg)
+        assert np.linalg.norm(c.rhs[0] - bt) <= 1e-10 * np.linalg.norm(c.rhs[0])
+        assert np.linalg.norm(xg - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+
+
+def test_pbicg_equals_pcg_on_symmetric_and_rejects_bad_options():
+    from paper_2512_22215_amd import LduError
+    c = CASES["c1"]
+    m = _lib().from_case(c)
+    xb, sb = m.pbicg(_t(c.rhs[0]), rel_tol=1e-8)
+    xc, sc = m.pcg(_t(c.rhs[0]), rel_tol=1e-8)
+    assert sb.iterations == sc.iterations
+    assert np.linalg.norm((xb - xc).cpu().numpy()) <= 1e-12 * np.linalg.norm(xc.cpu().numpy())
+    for bad in (dict(precond=2), dict(precision="mixed")):
+        with pytest.raises(LduError):
+            m.pbicg(_t(c.rhs[0]), **bad)
+
+
+def test_autograd_pbicg_nonsymmetric_matches_dense():
+    """Gradients through a non-symmetric solve (PBiCG forward and adjoint)
+    against dense linear algebra."""
+    from meshgen import config_case
+    from paper_2512_22215_amd import ldu_solve
+    c = config_case("c5u", n=9)
+    m = _lib().from_case(c)
+    d = _t(c.diag).requires_grad_(True)
+    u = _t(c.upper).requires_grad_(True)
+    lo = _t(c.lower).requires_grad_(True)
+    b = _t(c.rhs[0]).requires_grad_(True)
+    xt = np.random.default_rng(13).standard_normal(c.n_cells)
+    x = ldu_solve(d, u, lo, b, m, "pbicg", rel_tol=1e-13)
+    loss = 0.5 * torch.sum((x - _t(xt)) ** 2)
+    loss.backward()
+    D = np.zeros((c.n_cells, c.n_cells))
+    D[np.arange(c.n_cells), np.arange(c.n_cells)] = c.diag
+    D[c.owner, c.neighbour] = c.upper
+    D[c.neighbour, c.owner] = c.lower
+    xd = np.linalg.solve(D, c.rhs[0])
+    lam = np.linalg.solve(D.T, xd - xt)
+    assert np.linalg.norm(x.detach().cpu().numpy() - xd) <= 1e-10 * np.linalg.norm(xd)
+    for got, want in ((b.grad, lam), (d.grad, -lam * xd),
+                      (u.grad, -lam[c.owner] * xd[c.neighbour]),
+                      (lo.grad, -lam[c.neighbour] * xd[c.owner])):
+        g = got.cpu().numpy()
+        assert np.linalg.norm(g - want) <= 1e-9 * np.linalg.norm(want)

@@ -794,3 +794,44 @@ def test_aggressive_from_keeps_pairwise_levels_above():
                      passes=3, max_levels=2, n_coarsest=1)
         assert np.array_equal(gk.level(k).agg, sub.level(0).agg)
         assert gk.n_levels < g1.n_levels
+
+
+# ---------------------------------------------------------------- PBiCG
+
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("precond", [False, True])
+def test_pbicg_solves_nonsymmetric_dense(transpose, precond):
+    from meshgen import config_case
+    for c in (_perm_case(box_case(6, 5, 4, coeff="lognormal", nonsym=0.6, dirichlet_x0=1.0,
+                                  seed=71), 72),
+              config_case("c5u", n=7)):
+        A = O.Ldu.from_case(c)
+        D = dense_case(c)
+        r = O.pbicg(A, c.rhs[0], tol=1e-12, precond=precond, transpose=transpose)
+        xd = np.linalg.solve(D.T if transpose else D, c.rhs[0])
+        assert r.status == O.OK and r.true_residual <= 1e-12
+        assert np.linalg.norm(r.x - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+def test_pbicg_is_cg_on_symmetric_matrices():
+    """With A and M symmetric the shadow sequence equals the primal one, so
+    BiCG's recurrences are CG's, step for step."""
+    c = _perm_case(box_case(8, 7, 6, coeff="lognormal", dirichlet_x0=1.0, seed=73), 74)
+    A = O.Ldu.from_case(c)
+    for precond in (False, True):
+        rb = O.pbicg(A, c.rhs[0], tol=1e-10, precond=precond)
+        rc = O.pcg(A, c.rhs[0], tol=1e-10, precond=precond)
+        assert rb.iterations == rc.iterations
+        assert np.array_equal(rb.history, rc.history)
+        assert np.array_equal(rb.x, rc.x)
+
+
+def test_pbicg_zero_rhs_and_warm_start():
+    from meshgen import config_case
+    c = config_case("c5u", n=6)
+    A = O.Ldu.from_case(c)
+    r0 = O.pbicg(A, np.zeros(c.n_cells))
+    assert r0.status == O.OK and r0.iterations == 0 and not r0.x.any()
+    xd = np.linalg.solve(dense_case(c), c.rhs[0])
+    rw = O.pbicg(A, c.rhs[0], x0=xd, tol=1e-8)
+    assert rw.status == O.OK and rw.iterations <= 1

@@ -294,7 +294,39 @@ def main():
         mu.close()
         del mu, xu, bu
 
+        # pressure-equation assembly from geometry on the same mesh (face
+        # interpolation, Laplacian, negSumDiag, divergence) including the
+        # refresh of a cached GAMG hierarchy's Galerkin values
+        from meshgen import c3_assembly_inputs
+        ga = c3_assembly_inputs(n=args.n)
+        nfa = ga["owner"].size
+        ma = LduMatrix(ga["n"], torch.from_numpy(ga["owner"].astype(np.int32)).to(dev),
+                       torch.from_numpy(ga["neighbour"].astype(np.int32)).to(dev),
+                       torch.full((ga["n"],), -6.0, dtype=torch.float64, device=dev),
+                       torch.ones(nfa, dtype=torch.float64, device=dev),
+                       torch.ones(nfa, dtype=torch.float64, device=dev), device=dev)
+        aargs = [torch.from_numpy(ga[k]).to(dev) for k in ("gamma", "weights", "mag_sf", "delta")]
+        akw = {k: torch.from_numpy(ga[k]).to(dev) for k in ("diag_bc", "phi", "b_bc")}
+        asm = {}
+        for label, hier in (("assemble", False), ("assemble_and_refresh_gamg", True)):
+            if hier:
+                ma.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
+            ma.assemble_pressure(*aargs, **akw)
+            at = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ma.assemble_pressure(*aargs, **akw)
+                torch.cuda.synchronize()
+                at.append(time.perf_counter() - t0)
+            asm[label + "_ms"] = float(np.min(at)) * 1e3
+        log(f"[bench] pressure assembly {asm['assemble_ms']:.2f} ms, with GAMG refresh "
+            f"{asm['assemble_and_refresh_gamg_ms']:.2f} ms")
+        ma.close()
+        del ma, aargs, akw
+
     extra = {
+        "pressure_assembly": asm if not args.no_extra else None,
         "pbicg_nonsymmetric": bicg_rec,
         "variants": variants,
         "adjoint": adj_rec,

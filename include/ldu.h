@@ -227,6 +227,28 @@ int ldu_adjoint_solve(ldu_handle h, const double *g, double *lambda,
                       int solver, const void *opts, ldu_stats *stats,
                       void *hip_stream);
 
+/* Pressure-equation assembly on the handle's mesh, replacing its
+ * coefficients (the step before each pressure solve of a SIMPLE iteration;
+ * Sec. 4.3 profiles its negSumDiag, interpolation and divergence kernels):
+ *   gamma_f = w_f gamma[owner] + (1 - w_f) gamma[neighbour]
+ *   upper_f = lower_f = gamma_f mag_sf_f delta_f
+ *   diag_i  = -(sum of the off-diagonal coefficients in column i) - diag_bc_i
+ *   b_i     = sum_{owner(f)=i} phi_f - sum_{neighbour(f)=i} phi_f + b_bc_i
+ * gamma, diag_bc, b_bc, b: [n_cells]; weights, mag_sf, delta, phi: [n_faces]
+ * in the handle's face order; all device pointers.  diag_bc, b_bc may be
+ * NULL (zero); phi may be NULL (then b is not written); b is required with
+ * phi.  diag, upper, lower (may be NULL) receive copies of the assembled
+ * coefficients.  A cached GAMG hierarchy keeps its aggregation and gets new
+ * Galerkin values, as with ldu_set_coeffs.  Rows sum their faces in the
+ * serial face loop's order, so results are deterministic.  LDU_ERR_NAN if a
+ * coefficient comes out non-finite (the handle's values are then
+ * unspecified until the next successful assembly or ldu_set_coeffs). */
+int ldu_assemble_pressure(ldu_handle h, const double *gamma, const double *weights,
+                          const double *mag_sf, const double *delta,
+                          const double *diag_bc, const double *phi,
+                          const double *b_bc, double *b, double *diag,
+                          double *upper, double *lower, void *hip_stream);
+
 /* Gradients of a loss L through A x = b given lambda = A^-T dL/dx:
  * g_diag[i] = -lambda[i] x[i], g_upper[f] = -lambda[owner[f]] x[neighbour[f]],
  * g_lower[f] = -lambda[neighbour[f]] x[owner[f]] (and dL/db = lambda).

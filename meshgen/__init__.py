@@ -13,5 +13,6 @@ from .boxes import (  # noqa: F401
     rcm_order,
     random_order,
     config_case,
+    c3_assembly_inputs,
     CONFIG_NAMES,
 )

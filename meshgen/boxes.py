@@ -297,6 +297,32 @@ def config_c3(n=200, nxy=None) -> LduCase:
                    {"shape": (m, m, n)})
 
 
+def c3_assembly_inputs(n=200, nxy=None) -> dict:
+    """Geometry and fields for assembling the c3 pressure equation on the GPU:
+    the graded c3 box (dx = dy = 1/n, dz_k as c3), per internal face |S_f|,
+    the delta coefficient 1/|d_f| and the owner's linear-interpolation weight
+    w_f = (neighbour centre to face) / (centre to centre); per cell a
+    diffusivity gamma = exp(0.3 N(0,1)) (seed s = 6, a stand-in for 1/A_p),
+    the Dirichlet coefficient of the top layer gamma dx^2 / (dz_top / 2), a
+    face flux phi ~ N(0,1) dx^2 (s = 7) and zero boundary fluxes."""
+    dx, dz = c3_spacing(n)
+    m = n if nxy is None else nxy
+    own, nb, ax = box_faces(m, m, n)
+    N = m * m * n
+    kz = own // (m * m)
+    kz1 = np.minimum(kz + 1, n - 1)
+    mag_sf = np.where(ax < 2, dx * dz[kz], dx * dx)
+    delta = np.where(ax < 2, 1.0 / dx, 1.0 / (0.5 * (dz[kz] + dz[kz1])))
+    w = np.where(ax < 2, 0.5, dz[kz1] / (dz[kz] + dz[kz1]))
+    gamma = np.exp(0.3 * _rng(3, 6).standard_normal(N))
+    top = np.arange(N) // (m * m) == n - 1
+    diag_bc = np.where(top, gamma * dx * dx / (0.5 * dz[n - 1]), 0.0)
+    phi = _rng(3, 7).standard_normal(own.size) * dx * dx
+    return {"n": N, "owner": own, "neighbour": nb, "gamma": gamma, "weights": w,
+            "mag_sf": mag_sf, "delta": delta, "diag_bc": diag_bc, "phi": phi,
+            "b_bc": np.zeros(N), "shape": (m, m, n)}
+
+
 def config_c4(n=256, order="rcm") -> LduCase:
     """256^3 box, a_f = exp(N(0,1)), Dirichlet at x = 0 with a_b = 2, RCM
     numbering; three rhs ~ N(0,1) solved back to back with warm starts."""

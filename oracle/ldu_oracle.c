@@ -1472,3 +1472,46 @@ void orc_coeff_grad(int32_t n, int64_t nf, const int32_t *own,
         g_lower[f] = -(lambda[nb[f]] * x[own[f]]);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pressure-equation assembly, the step before the solve in every SIMPLE     */
+/* iteration (Sec. 4.3 profile: lduMatrix::negSumDiag, the interpolation and */
+/* divergence kernels; the pressure-assembly rows of the scaling tables):    */
+/*   gamma_f = w_f gamma[own] + (1 - w_f) gamma[nb]   (linear interpolation) */
+/*   upper_f = lower_f = gamma_f |S_f| delta_f         (fvm::laplacian)       */
+/*   diag_i  = -(off-diagonal sum of column i) - diag_bc_i   (negSumDiag:    */
+/*             diag[own] -= lower_f, diag[nb] -= upper_f, in face order)     */
+/*   b_i     = sum_{own(f)=i} phi_f - sum_{nb(f)=i} phi_f + b_bc_i  (fvc::div) */
+/* The _bc terms carry the boundary faces (Dirichlet coefficients, boundary  */
+/* fluxes).  phi, b_bc and b may be NULL (no right-hand side).               */
+/* Pins: closed-form 7-point stencil, zero column sums, telescoping          */
+/* divergence, exact interpolation of linear fields.                         */
+/* ------------------------------------------------------------------------ */
+void orc_assemble_pressure(int32_t n, int64_t nf, const int32_t *own,
+                           const int32_t *nb, const double *gamma,
+                           const double *w, const double *mag_sf,
+                           const double *delta, const double *diag_bc,
+                           const double *phi, const double *b_bc, double *diag,
+                           double *upper, double *lower, double *b) {
+    for (int64_t f = 0; f < nf; ++f) {
+        const double gf = w[f] * gamma[own[f]] + (1.0 - w[f]) * gamma[nb[f]];
+        upper[f] = gf * mag_sf[f] * delta[f];
+        lower[f] = upper[f];
+    }
+    for (int32_t i = 0; i < n; ++i) diag[i] = 0.0;
+    for (int64_t f = 0; f < nf; ++f) {
+        diag[own[f]] -= lower[f];
+        diag[nb[f]] -= upper[f];
+    }
+    if (diag_bc)
+        for (int32_t i = 0; i < n; ++i) diag[i] = diag[i] - diag_bc[i];
+    if (phi && b) {
+        for (int32_t i = 0; i < n; ++i) b[i] = 0.0;
+        for (int64_t f = 0; f < nf; ++f) {
+            b[own[f]] += phi[f];
+            b[nb[f]] -= phi[f];
+        }
+        if (b_bc)
+            for (int32_t i = 0; i < n; ++i) b[i] = b[i] + b_bc[i];
+    }
+}

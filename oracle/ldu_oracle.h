@@ -150,6 +150,16 @@ void orc_coeff_grad(int32_t n, int64_t nf, const int32_t *own,
                     const int32_t *nb, const double *lambda, const double *x,
                     double *g_diag, double *g_upper, double *g_lower);
 
+/* pressure-equation assembly: linear interpolation of gamma to the faces,
+ * fvm::laplacian coefficients, negSumDiag, divergence of phi (phi, b_bc, b
+ * may be NULL; diag_bc may be NULL) */
+void orc_assemble_pressure(int32_t n, int64_t nf, const int32_t *own,
+                           const int32_t *nb, const double *gamma,
+                           const double *w, const double *mag_sf,
+                           const double *delta, const double *diag_bc,
+                           const double *phi, const double *b_bc, double *diag,
+                           double *upper, double *lower, double *b);
+
 #ifdef __cplusplus
 }
 #endif

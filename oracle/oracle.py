@@ -70,6 +70,8 @@ def lib():
     L.orc_pcg.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p,
                           d, C.c_int, C.c_int, C.c_int, ip, _f64o, dp]
     L.orc_pbicg.argtypes = L.orc_pcg.argtypes
+    L.orc_assemble_pressure.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p,
+                                        _f64o, _f64o, _f64o, _f64p, _f64p, _f64p, _f64o]
     L.orc_pcg_mixed.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p,
                                 _f64p, d, C.c_int, d, C.c_int, C.c_int, ip, ip, _f64o, dp]
     L.orc_gamg_build.restype = vp
@@ -368,3 +370,21 @@ def dic(A: Ldu, r=None):
     z = None if r is None else np.empty(A.n)
     ok = lib().orc_dic(*A.args(), dt, None if r is None else _c(r, np.float64), z)
     return dt, bool(ok), z
+
+
+def assemble_pressure(n, owner, neighbour, gamma, weights, mag_sf, delta, diag_bc=None,
+                      phi=None, b_bc=None):
+    """Pressure-equation assembly: returns (diag, upper, lower, b or None)."""
+    own = _c(owner, np.int32)
+    nb = _c(neighbour, np.int32)
+    nf = own.size
+    diag = np.empty(n)
+    up = np.empty(nf)
+    lo = np.empty(nf)
+    b = None if phi is None else np.empty(n)
+    opt = lambda a: None if a is None else _c(a, np.float64)
+    lib().orc_assemble_pressure(int(n), int(nf), own, nb, _c(gamma, np.float64),
+                                _c(weights, np.float64), _c(mag_sf, np.float64),
+                                _c(delta, np.float64), opt(diag_bc), opt(phi), opt(b_bc),
+                                diag, up, lo, b)
+    return diag, up, lo, b

@@ -237,6 +237,33 @@ int ldu_set_coeffs(ldu_handle h, const double *diag, const double *upper, const 
     });
 }
 
+int ldu_assemble_pressure(ldu_handle h, const double *gamma, const double *weights,
+                          const double *mag_sf, const double *delta, const double *diag_bc,
+                          const double *phi, const double *b_bc, double *b, double *diag,
+                          double *upper, double *lower, void *hip_stream) {
+    if (!h) return fail(LDU_ERR_ARG, "NULL handle");
+    if (!gamma || (h->L0.nf > 0 && (!weights || !mag_sf || !delta)) || (phi && !b))
+        return fail(LDU_ERR_ARG, "NULL array");
+    return guarded(h, [&] {
+        hipStream_t st = S(hip_stream);
+        Level &L = h->L0;
+        assemble_pressure(h, gamma, weights, mag_sf, delta, diag_bc, phi, b_bc, b, st);
+        HIP_CHECK(hipMemsetAsync(h->flag, 0, sizeof(int), st));
+        check_finite(h, L.diag, L.n, st);
+        if (L.nf > 0) check_finite(h, L.upper, L.nf, st);
+        HIP_CHECK(hipMemcpyAsync(h->hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        if (*h->hflag) throw Error(LDU_ERR_NAN, "non-finite assembled coefficient");
+        refresh_f32(L, st);
+        gamg_refresh_values(h, st);
+        if (diag) copy_in(diag, L.diag, sizeof(double) * L.n, st);
+        if (upper) copy_in(upper, L.upper, sizeof(double) * L.nf, st);
+        if (lower) copy_in(lower, L.lower, sizeof(double) * L.nf, st);
+        HIP_CHECK(hipStreamSynchronize(st));
+        return LDU_OK;
+    });
+}
+
 int ldu_amul(ldu_handle h, const double *x, double *y, void *hip_stream) {
     if (!h || !x || !y) return fail(LDU_ERR_ARG, "NULL argument");
     return guarded(h, [&] {

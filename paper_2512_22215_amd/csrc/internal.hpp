@@ -201,6 +201,9 @@ inline int64_t slices_of(int64_t n) { return (n + kWave - 1) / kWave; }
 // relayout.hip
 void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t st);
 void set_level_values(Level &L, hipStream_t st);   // face values -> SELL values
+void assemble_pressure(ldu_t *h, const double *gamma, const double *w, const double *mag_sf,
+                       const double *delta, const double *diag_bc, const double *phi,
+                       const double *b_bc, double *b, hipStream_t st);
 void ensure_f32(Level &L, Arena &ar, hipStream_t st);
 void refresh_f32(Level &L, hipStream_t st);
 void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, Arena &tmp,

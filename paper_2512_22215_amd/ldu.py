@@ -25,7 +25,7 @@ EXPORTED = (
     "ldu_pcg_default_opts", "ldu_gamg_default_opts", "ldu_create", "ldu_set_coeffs",
     "ldu_destroy", "ldu_amul", "ldu_tmul", "ldu_amul_f32", "ldu_residual", "pcg_solve",
     "pbicg_solve", "gamg_setup", "gamg_solve", "gamg_vcycle", "gamg_level_size", "gamg_level_export",
-    "ldu_adjoint_solve", "ldu_coeff_grad", "ldu_last_error",
+    "ldu_adjoint_solve", "ldu_coeff_grad", "ldu_assemble_pressure", "ldu_last_error",
 )
 
 
@@ -104,6 +104,7 @@ def lib():
     L.gamg_level_export.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp]
     L.ldu_adjoint_solve.argtypes = [vp, vp, vp, i, vp, C.POINTER(Stats), vp]
     L.ldu_coeff_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.ldu_assemble_pressure.argtypes = [vp] * 13
     L.ldu_last_error.restype = C.c_char_p
     for name in EXPORTED:
         if name != "ldu_last_error" and name not in ("ldu_pcg_default_opts",
@@ -207,6 +208,12 @@ class LduMatrix:
 
     def _vec(self, x, dtype=torch.float64):
         return _dev(x, dtype, self.device)
+
+    def _sized(self, x, count, what):
+        t = self._vec(x)
+        if t.numel() != count:
+            raise ValueError(f"{what}: {t.numel()} values, expected {count}")
+        return t
 
     def set_coeffs(self, diag, upper, lower):
         d, u, l = (self._vec(v) for v in (diag, upper, lower))
@@ -314,6 +321,31 @@ class LduMatrix:
                                      _stream())
         _check(rc)
         return lam, _stats_out(rc, st, buf)
+
+    def assemble_pressure(self, gamma, weights, mag_sf, delta, diag_bc=None, phi=None,
+                          b_bc=None, out_coeffs=False):
+        """Assemble the pressure equation on this mesh (replaces the
+        coefficients).  Returns b (or None without phi), plus (diag, upper,
+        lower) copies when out_coeffs."""
+        n, nf = self.n, self.nf
+        gamma = self._sized(gamma, n, "gamma")
+        weights = self._sized(weights, nf, "weights")
+        mag_sf = self._sized(mag_sf, nf, "mag_sf")
+        delta = self._sized(delta, nf, "delta")
+        diag_bc = None if diag_bc is None else self._sized(diag_bc, n, "diag_bc")
+        b_bc = None if b_bc is None else self._sized(b_bc, n, "b_bc")
+        phi = None if phi is None else self._sized(phi, nf, "phi")
+        b = None if phi is None else torch.empty(self.n, dtype=torch.float64,
+                                                 device=self.device)
+        outs = [None, None, None]
+        if out_coeffs:
+            outs = [torch.empty(k, dtype=torch.float64, device=self.device)
+                    for k in (self.n, self.nf, self.nf)]
+        p = lambda t: None if t is None else _ptr(t)
+        _check(lib().ldu_assemble_pressure(self._h, p(gamma), p(weights), p(mag_sf), p(delta),
+                                           p(diag_bc), p(phi), p(b_bc), p(b), p(outs[0]),
+                                           p(outs[1]), p(outs[2]), _stream()), False)
+        return (b, tuple(outs)) if out_coeffs else b
 
     def coeff_grad(self, lam, x):
         lam, x = self._vec(lam), self._vec(x)

@@ -523,3 +523,51 @@ def test_autograd_pbicg_nonsymmetric_matches_dense():
                       (lo.grad, -lam[c.neighbour] * xd[c.owner])):
         g = got.cpu().numpy()
         assert np.linalg.norm(g - want) <= 1e-9 * np.linalg.norm(want)
+
+
+def _assembly_matrix(g):
+    """A handle on the assembly mesh, created with placeholder coefficients."""
+    from paper_2512_22215_amd import LduMatrix
+    nf = g["owner"].size
+    return LduMatrix(g["n"], _t(g["owner"].astype(np.int32)), _t(g["neighbour"].astype(np.int32)),
+                     _t(-6.0 * np.ones(g["n"])), _t(np.ones(nf)), _t(np.ones(nf)), device="cuda")
+
+
+def test_pressure_assembly_bit_exact_and_feeds_the_solvers():
+    from meshgen import c3_assembly_inputs
+    g = c3_assembly_inputs(n=24, nxy=10)
+    m = _assembly_matrix(g)
+    m.gamg_setup()  # a cached hierarchy must pick up the new values
+    args = [g[k] for k in ("gamma", "weights", "mag_sf", "delta")]
+    b, (d, u, lo) = m.assemble_pressure(*args, diag_bc=g["diag_bc"], phi=g["phi"],
+                                        b_bc=g["b_bc"], out_coeffs=True)
+    rd, ru, rl, rb = O.assemble_pressure(g["n"], g["owner"], g["neighbour"], *args,
+                                         g["diag_bc"], g["phi"], g["b_bc"])
+    for got, want in ((d, rd), (u, ru), (lo, rl), (b, rb)):
+        assert np.array_equal(got.cpu().numpy(), want)
+    A = O.Ldu(g["n"], g["owner"], g["neighbour"], rd, ru, rl)
+    # the handle now holds the assembled matrix: products, hierarchy, solve
+    x = np.random.default_rng(21).standard_normal(g["n"])
+    assert np.array_equal(m.amul(_t(x)).cpu().numpy(), O.amul(A, x))
+    # the cached aggregation is the placeholder matrix's; its Galerkin values
+    # are recomputed from the assembled ones
+    nf = g["owner"].size
+    ref = O.Gamg(O.Ldu(g["n"], g["owner"], g["neighbour"], -6.0 * np.ones(g["n"]),
+                       np.ones(nf), np.ones(nf)))
+    ref.set_values(rd, ru, rl)
+    assert m.n_levels() == ref.n_levels
+    for l in range(ref.n_levels):
+        lv = m.level(l)
+        assert np.array_equal(lv["diag"].cpu().numpy(), ref.level(l).diag), l
+        assert np.array_equal(lv["upper"].cpu().numpy(), ref.level(l).upper), l
+    rhs = rb + 0.1 * np.random.default_rng(22).standard_normal(g["n"])
+    xs, st = m.pcg(_t(rhs), precond=2, rel_tol=1e-8, max_iter=2000)
+    assert st.converged
+    assert np.linalg.norm(rhs - O.amul(A, xs.cpu().numpy())) <= 1e-8 * np.linalg.norm(rhs)
+    # optional inputs: no boundary terms, no right-hand side
+    assert m.assemble_pressure(*args) is None
+    rd0, _, _, _ = O.assemble_pressure(g["n"], g["owner"], g["neighbour"], *args)
+    _, (d0, _, _) = m.assemble_pressure(*args, out_coeffs=True)
+    assert np.array_equal(d0.cpu().numpy(), rd0)
+    with pytest.raises(ValueError):
+        m.assemble_pressure(g["gamma"][:-1], *args[1:])

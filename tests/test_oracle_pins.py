@@ -10,8 +10,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from meshgen import (assemble_diag, box_case, box_faces, config_case,
-                     random_order, relabel)
+from meshgen import (assemble_diag, box_case, box_faces, c3_assembly_inputs,
+                     config_case, random_order, relabel)
 from meshgen.boxes import LduCase, c3_spacing
 from tests.dense_ref import (closed_form_1d, dense, dense_case,
                              galerkin_ldu, greedy_matching,
@@ -835,3 +835,54 @@ def test_pbicg_zero_rhs_and_warm_start():
     xd = np.linalg.solve(dense_case(c), c.rhs[0])
     rw = O.pbicg(A, c.rhs[0], x0=xd, tol=1e-8)
     assert rw.status == O.OK and rw.iterations <= 1
+
+
+# ---------------------------------------------------------------- pressure assembly
+
+def test_assembly_uniform_box_is_the_seven_point_stencil():
+    """gamma = 1 on a uniform box with spacing h: every face coefficient is
+    |S| / |d| = h, and the matrix is h times the 7-point Laplacian (closed
+    form: dense stencil built from cell coordinates)."""
+    n = 5
+    h = 1.0 / n
+    own, nb, ax = box_faces(n, n, n)
+    N = n ** 3
+    d, u, lo, _ = O.assemble_pressure(N, own, nb, np.ones(N), np.full(own.size, 0.5),
+                                      np.full(own.size, h * h), np.full(own.size, 1.0 / h))
+    assert np.allclose(u, h, rtol=1e-15) and np.array_equal(u, lo)
+    ijk = np.stack(np.unravel_index(np.arange(N), (n, n, n)), 1)
+    S = np.zeros((N, N))
+    for i in range(N):
+        for j in range(N):
+            if np.abs(ijk[i] - ijk[j]).sum() == 1:
+                S[i, j] = h
+    np.fill_diagonal(S, -S.sum(1))
+    assert np.allclose(dense(N, own, nb, d, u, lo), S, rtol=0, atol=1e-15)
+
+
+def test_assembly_column_sums_divergence_and_interpolation():
+    g = c3_assembly_inputs(n=12)
+    N, own, nb = g["n"], g["owner"], g["neighbour"]
+    d, u, lo, b = O.assemble_pressure(N, own, nb, g["gamma"], g["weights"], g["mag_sf"],
+                                      g["delta"], g["diag_bc"], g["phi"], g["b_bc"])
+    A = dense(N, own, nb, d, u, lo)
+    # negSumDiag: each column sums to minus its boundary coefficient
+    assert np.allclose(A.sum(0), -g["diag_bc"], rtol=0, atol=1e-13 * np.abs(d).max())
+    # divergence telescopes: interior fluxes cancel in the total
+    assert abs(b.sum() - g["b_bc"].sum()) <= 1e-14 * np.abs(g["phi"]).sum()
+    # a uniform flux through x faces only leaves sources on the x = 0 / x = end layers
+    phi_x = np.where(own + 1 == nb, 1.0, 0.0)
+    _, _, _, bx = O.assemble_pressure(N, own, nb, g["gamma"], g["weights"], g["mag_sf"],
+                                      g["delta"], phi=phi_x)
+    m = g["shape"][0]
+    ix = np.arange(N) % m
+    assert np.all(bx[(ix > 0) & (ix < m - 1)] == 0.0)
+    assert np.all(bx[ix == 0] == 1.0) and np.all(bx[ix == m - 1] == -1.0)
+    # linear interpolation is exact for a field linear in z (graded spacing)
+    dx, dz = c3_spacing(g["shape"][2])
+    zc = np.cumsum(dz) - 0.5 * dz
+    z = zc[np.arange(N) // (m * m)]
+    _, uz, _, _ = O.assemble_pressure(N, own, nb, 1.0 + z, g["weights"],
+                                      np.ones(own.size), np.ones(own.size))
+    zf = np.where(nb - own == m * m, np.cumsum(dz)[own // (m * m)], z[own])
+    assert np.allclose(uz, 1.0 + zf, rtol=1e-14, atol=0)

@@ -825,16 +825,31 @@ __device__ __forceinline__ double readlane_f64(double v, int j) {
 // the sparse kernels do.
 constexpr int kWaveRow = 48;
 
-__global__ void __launch_bounds__(kWave)
-k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
-                const float *__restrict__ rhs_f, double *__restrict__ eo_d,
-                float *__restrict__ eo_f, int singular, double tol, int max_it,
-                const double *__restrict__ dt, FineCorr<double> fcd, FineCorr<float> fcf,
-                const DevScalars *ds) {
-    __shared__ int32_t cL[kWaveRow * kWave];
-    __shared__ double vL[kWaveRow * kWave];
-    __shared__ double p[kWave];
-    if (vc_skip(ds)) return;
+// LDS ordering for one wavefront: its LDS operations execute in order, so a
+// fence against compiler reordering is all a lane-to-lane exchange needs
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct CoarsestLds {
+    int32_t cL[kWaveRow * kWave];
+    double vL[kWaveRow * kWave];
+    double p[kWave];
+};
+
+// the one-wavefront coarsest CG, run by the 64 lanes of one wave (the
+// caller's other waves, if any, do not take part)
+__device__ void coarsest_wave_body(const SellView<double> &A, const double *__restrict__ rhs_d,
+                                   const float *__restrict__ rhs_f, double *__restrict__ eo_d,
+                                   float *__restrict__ eo_f, int singular, double tol,
+                                   int max_it, const double *__restrict__ dt,
+                                   const FineCorr<double> &fcd, const FineCorr<float> &fcf,
+                                   CoarsestLds &sm) {
+    int32_t *cL = sm.cL;
+    double *vL = sm.vL;
+    double *p = sm.p;
     const int32_t n = A.n;
     const int i = threadIdx.x;
     double di = 1.0, ri = 0.0, rdt = 0.0;
@@ -855,7 +870,7 @@ k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
         ri = rhs_d ? rhs_d[i] : (double)rhs_f[i];
         if (dt) rdt = 1.0 / dt[i];
     }
-    __syncthreads();
+    wave_lds_sync();
     // z = M^-1 r: the diagonal, or the DIC factor by column-oriented
     // substitution: at step j lane j's value is final and is broadcast, and
     // every row holding column j takes its term (lower entries in ascending
@@ -899,13 +914,13 @@ k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
         double rho = wave_sum(ri * pi);
         for (int it = 0; it < max_it; ++it) {
             p[i] = pi;
-            __syncthreads();
+            wave_lds_sync();
             double qi = 0.0;
             if (i < n) {
                 qi = di * pi;
                 for (int k = 0; k < m; ++k) qi = qi + vL[k * kWave + i] * p[cL[k * kWave + i]];
             }
-            __syncthreads();
+            wave_lds_sync();
             const double pq = wave_sum(pi * qi);
             if (!isfinite(pq) || fabs(pq) <= 1e-300) break;
             const double alpha = rho / pq;
@@ -930,6 +945,17 @@ k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
             if (fcf.e) fcf(i, v);
         }
     }
+}
+
+__global__ void __launch_bounds__(kWave)
+k_coarsest_wave(SellView<double> A, const double *__restrict__ rhs_d,
+                const float *__restrict__ rhs_f, double *__restrict__ eo_d,
+                float *__restrict__ eo_f, int singular, double tol, int max_it,
+                const double *__restrict__ dt, FineCorr<double> fcd, FineCorr<float> fcf,
+                const DevScalars *ds) {
+    __shared__ CoarsestLds sm;
+    if (vc_skip(ds)) return;
+    coarsest_wave_body(A, rhs_d, rhs_f, eo_d, eo_f, singular, tol, max_it, dt, fcd, fcf, sm);
 }
 
 // coarsest-level launch for larger levels: one 256-thread block
@@ -1071,6 +1097,7 @@ float *lvec<float>(Level &L, int which) {
 }
 
 constexpr int kFuseCorrRows = 1 << 17;
+
 
 // One V-cycle e = V(l, r); returns the buffer holding e.  With rdot, the
 // last level-l kernel also leaves the block partials of rdot . e in

@@ -236,8 +236,9 @@ int ldu_adjoint_solve(ldu_handle h, const double *g, double *lambda,
  *   b_i     = sum_{owner(f)=i} phi_f - sum_{neighbour(f)=i} phi_f + b_bc_i
  * gamma, diag_bc, b_bc, b: [n_cells]; weights, mag_sf, delta, phi: [n_faces]
  * in the handle's face order; all device pointers.  diag_bc, b_bc may be
- * NULL (zero); phi may be NULL (then b is not written); b is required with
- * phi.  diag, upper, lower (may be NULL) receive copies of the assembled
+ * NULL (zero).  b may be NULL (no right-hand side); when it is given, phi is
+ * required unless the mesh has no faces, and a phi without b is an error.
+ * diag, upper, lower (may be NULL) receive copies of the assembled
  * coefficients.  A cached GAMG hierarchy keeps its aggregation and gets new
  * Galerkin values, as with ldu_set_coeffs.  Rows sum their faces in the
  * serial face loop's order, so results are deterministic.  LDU_ERR_NAN if a

@@ -242,7 +242,8 @@ int ldu_assemble_pressure(ldu_handle h, const double *gamma, const double *weigh
                           const double *phi, const double *b_bc, double *b, double *diag,
                           double *upper, double *lower, void *hip_stream) {
     if (!h) return fail(LDU_ERR_ARG, "NULL handle");
-    if (!gamma || (h->L0.nf > 0 && (!weights || !mag_sf || !delta)) || (phi && !b))
+    if (!gamma || (h->L0.nf > 0 && (!weights || !mag_sf || !delta || (b && !phi))) ||
+        (phi && !b))
         return fail(LDU_ERR_ARG, "NULL array");
     return guarded(h, [&] {
         hipStream_t st = S(hip_stream);

@@ -45,7 +45,7 @@ k_asm_rows(Sell A, const int64_t *__restrict__ own_start, const int32_t *__restr
         double d = 0.0;
         for (int k = 0; k < w; ++k) d = d - A.valT[entry_at(A, p, k)];
         diag[i] = diag_bc ? d - diag_bc[i] : d;
-        if (!phi) return;
+        if (!b) return;  // phi is read only through faces, so it may be null without any
         double acc = 0.0;
         for (int k = 0; k < w; ++k) {
             const int32_t c = A.col[entry_at(A, p, k)];

@@ -169,3 +169,25 @@ def test_c3_pressure_assembly_bit_exact():
     for got, want in ((d, rd), (u, ru), (lo, rl), (b, rb)):
         assert np.array_equal(got.cpu().numpy(), want)
     m.close()
+
+
+def test_c5u_pbicg_nonsymmetric():
+    """PBiCG on the 1M-cell convection-diffusion box: the oracle's residual
+    of the GPU solution, forward and adjoint, and the oracle's own solve."""
+    from paper_2512_22215_amd import LduMatrix
+    c = config_case("c5u")
+    m = LduMatrix.from_case(c)
+    A = O.Ldu.from_case(c)
+    b = c.rhs[0]
+    x, st = m.pbicg(_t(b), rel_tol=1e-10, max_iter=5000)
+    xn = x.cpu().numpy()
+    assert st.converged and _res(A, b, xn) <= 1e-10
+    ref = O.pbicg(A, b, tol=1e-10, max_iter=5000)
+    assert ref.status == O.OK
+    assert abs(st.iterations - ref.iterations) <= max(1, ref.iterations // 10)
+    assert np.linalg.norm(xn - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+    lam, sa = m.adjoint(_t(b), solver="pbicg", rel_tol=1e-10, max_iter=5000)
+    ln = lam.cpu().numpy()
+    assert sa.converged
+    assert np.linalg.norm(b - O.tmul(A, ln)) <= 1e-10 * np.linalg.norm(b)
+    m.close()

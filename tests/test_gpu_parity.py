@@ -571,3 +571,29 @@ def test_pressure_assembly_bit_exact_and_feeds_the_solvers():
     assert np.array_equal(d0.cpu().numpy(), rd0)
     with pytest.raises(ValueError):
         m.assemble_pressure(g["gamma"][:-1], *args[1:])
+
+
+@pytest.mark.parametrize("n", [1, 70])
+def test_solvers_on_matrices_without_faces(n):
+    """Degenerate inputs: one cell, or a diagonal matrix with no faces (one
+    GAMG level, which is its own coarsest level; for 70 cells the workgroup
+    coarsest kernel).  Every solver returns D^-1 b; the assembly leaves
+    diag = -diag_bc and b = b_bc."""
+    from meshgen.boxes import LduCase
+    e = np.zeros(0, np.int32)
+    d = -1.0 - np.arange(n, dtype=np.float64)
+    b = np.random.default_rng(31).standard_normal(n)
+    c = LduCase("diag", n, e, e.copy(), d, np.zeros(0), np.zeros(0), [b], False)
+    m = _lib().from_case(c)
+    want = b / d
+    for x, st in (m.pcg(_t(b)), m.pcg(_t(b), precond=2), m.gamg(_t(b)), m.pbicg(_t(b)),
+                  m.pcg(_t(b), precision="mixed"), m.gamg(_t(b), precision="mixed")):
+        assert st.converged
+        assert np.allclose(x.cpu().numpy(), want, rtol=1e-8, atol=0)
+    assert m.n_levels() == 1
+    bc = np.abs(b)
+    bb, (dd, uu, ll) = m.assemble_pressure(np.ones(n), np.zeros(0), np.zeros(0), np.zeros(0),
+                                           diag_bc=bc, phi=np.zeros(0), b_bc=b,
+                                           out_coeffs=True)
+    assert np.array_equal(dd.cpu().numpy(), -bc) and np.array_equal(bb.cpu().numpy(), b)
+    assert uu.numel() == 0 and ll.numel() == 0

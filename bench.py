@@ -107,6 +107,98 @@ def cpu_baseline(iters_gpu, n=200, nxy=100, sample_iters=3):
     }
 
 
+def _timed(torch, fn, reps=2):
+    """One warm-up call, then the best of reps timed calls (seconds)."""
+    out = fn()
+    best = float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best, out
+
+
+def run_suite(torch, dev):
+    """The runs each workload is defined for, timed on the GPU: c1 PCG; c2
+    PCG, GAMG and CG + V-cycle in random and RCM numbering; c4 PCG FP64 and
+    mixed over three warm-started right-hand sides, plus CG + V-cycle; c5
+    forward and adjoint with the coefficient gradients.  Every solve is checked
+    against its tolerance through the library's FP64 residual."""
+    from meshgen import config_case
+    from paper_2512_22215_amd import LduMatrix
+
+    def tens(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    def solve_rec(m, b, fn, **kw):
+        t, (x, st) = _timed(torch, lambda: fn(b, **kw))
+        res = m.residual(b, x)
+        assert st.converged and res <= kw.get("rel_tol", 1e-8) * 1.0000001, (kw, st, res)
+        return {"s": t, "iterations": st.iterations, "refinements": st.refinements,
+                "true_residual": res}
+
+    def amul_rec(m, case):
+        x = torch.randn(case.n_cells, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        t = time_kernel(lambda: m.amul(x, out=y), 100, torch)
+        return {"us": t * 1e6, "GBps": amul_bytes(case.n_cells, case.n_faces) / t / 1e9}
+
+    for name, kw in (("c1", {}), ("c2", {"order": "random"}), ("c2", {"order": "rcm"}),
+                     ("c4", {}), ("c5", {})):
+        t0 = time.perf_counter()
+        case = config_case(name, **kw)
+        log(f"[suite] {case.name}: {case.n_cells} cells ({time.perf_counter() - t0:.1f} s "
+            f"to generate)")
+        m = LduMatrix.from_case(case)
+        rec = {"workload": case.name, "cells": case.n_cells, "faces": case.n_faces,
+               "amul_f64": amul_rec(m, case)}
+        b = tens(case.rhs[0])
+        if name == "c1":
+            rec["pcg_diag_fp64"] = solve_rec(m, b, m.pcg, rel_tol=1e-8)
+        elif name == "c2":
+            rec["pcg_diag_fp64"] = solve_rec(m, b, m.pcg, rel_tol=1e-8)
+            m.gamg_setup(n_pre=1, n_post=1)
+            rec["levels"] = m.n_levels()
+            rec["gamg_fp64"] = solve_rec(m, b, m.gamg, rel_tol=1e-8, n_pre=1, n_post=1,
+                                         max_cycles=1000)
+            rec["pcg_gamg_fp64"] = solve_rec(m, b, m.pcg, rel_tol=1e-8, precond=2)
+        elif name == "c4":
+            m.gamg_setup(n_pre=1, n_post=1)
+            rec["levels"] = m.n_levels()
+            for label, kwp in (("pcg_diag", dict(rel_tol=1e-8)),
+                               ("pcg_gamg", dict(rel_tol=1e-8, precond=2))):
+                for prec in ("fp64", "mixed"):
+                    runs = []
+                    xk = torch.zeros(case.n_cells, dtype=torch.float64, device=dev)
+                    for rk in case.rhs:  # back to back, each warm-started from the last
+                        bk = tens(rk)
+                        torch.cuda.synchronize()
+                        t1 = time.perf_counter()
+                        xk, st = m.pcg(bk, x0=xk, precision=prec, **kwp)
+                        torch.cuda.synchronize()
+                        dt = time.perf_counter() - t1
+                        res = m.residual(bk, xk)
+                        assert st.converged and res <= 1e-8, (label, prec, st, res)
+                        runs.append({"s": dt, "iterations": st.iterations,
+                                     "refinements": st.refinements, "true_residual": res})
+                    rec[f"{label}_{prec}_3rhs"] = runs
+        elif name == "c5":
+            rec["pcg_diag_fp64"] = solve_rec(m, b, m.pcg, rel_tol=1e-8)
+            rec["pcg_diag_mixed"] = solve_rec(m, b, m.pcg, rel_tol=1e-8, precision="mixed")
+            t, (x, _) = _timed(torch, lambda: m.pcg(b, rel_tol=1e-11, max_iter=5000))
+            g = x - tens(case.meta["x_target"])
+            ta, (lam, sa) = _timed(torch, lambda: m.adjoint(g, rel_tol=1e-11, max_iter=5000))
+            tg = time_kernel(lambda: m.coeff_grad(lam, x), 20, torch)
+            rec["forward_fp64_1e-11_s"] = t
+            rec["adjoint_fp64_1e-11"] = {"s": ta, "iterations": sa.iterations}
+            rec["coeff_grad_us"] = tg * 1e6
+        m.close()
+        log(f"[suite] {json.dumps(rec)}")
+        print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +213,9 @@ def main():
                     help="only the Amul and copy timings (for counter runs)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the mixed, adjoint and variant solves (for kernel traces)")
+    ap.add_argument("--suite", action="store_true",
+                    help="instead of the headline step, time the runs of every workload "
+                         "(c1, c2 random and RCM, c4, c5), one JSON line each")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -133,6 +228,9 @@ def main():
     from paper_2512_22215_amd import LduMatrix
 
     dev = torch.device("cuda:0")
+    if args.suite:
+        run_suite(torch, dev)
+        return
     t0 = time.perf_counter()
     case = config_case("c3", n=args.n)
     log(f"[bench] workload c3 n={args.n}: {case.n_cells} cells, {case.n_faces} faces "

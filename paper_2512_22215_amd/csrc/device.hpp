@@ -37,15 +37,42 @@ __device__ __forceinline__ void for_each_slice(int64_t S, F &&f) {
     }
 }
 
+// Wavefront reductions with DPP lane moves (no LDS round trips): pairs and
+// quads (quad_perm), the 16-lane rows (row_ror 4, 8), then row 0 into row 1
+// and row 2 into row 3 (row_bcast 15), rows 0-1 into rows 2-3 (row_bcast
+// 31); lane 63 ends with the total, which every lane then reads.  The order
+// is fixed, so results are reproducible.  A lane the move does not write
+// keeps `old` (0 for sums, its own value for maxima).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v, double old) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL,
+                                               ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL,
+                                               ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane63(double v) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = v + dpp_move<0xB1>(v, 0.0);        // quad_perm [1,0,3,2]
+    v = v + dpp_move<0x4E>(v, 0.0);        // quad_perm [2,3,0,1]
+    v = v + dpp_move<0x124>(v, 0.0);       // row_ror 4
+    v = v + dpp_move<0x128>(v, 0.0);       // row_ror 8
+    v = v + dpp_move<0x142, 0xa>(v, 0.0);  // row_bcast 15
+    v = v + dpp_move<0x143, 0xc>(v, 0.0);  // row_bcast 31
+    return lane63(v);
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
+    v = fmax(v, dpp_move<0xB1>(v, v));
+    v = fmax(v, dpp_move<0x4E>(v, v));
+    v = fmax(v, dpp_move<0x124>(v, v));
+    v = fmax(v, dpp_move<0x128>(v, v));
+    v = fmax(v, dpp_move<0x142, 0xa>(v, v));
+    v = fmax(v, dpp_move<0x143, 0xc>(v, v));
+    return lane63(v);
 }
 
 // block-wide reduction of K values (slots >= K - M take the max, the others

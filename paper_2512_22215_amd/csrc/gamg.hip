@@ -232,6 +232,90 @@ __global__ void k_coarse_values(int64_t ncf, const int32_t *cown, const int32_t 
     }
 }
 
+// The same visits recorded once (count, then fill), so that new fine values
+// only need a pass over the lists: each sum keeps its order and its bits.
+// LIST = false counts, LIST = true writes at the counted offsets.
+template <bool LIST>
+__global__ void k_coarse_facelist(int64_t ncf, const int32_t *cown, const int32_t *cnb,
+                                  const int32_t *agg, const int32_t *start,
+                                  const int32_t *cells, const int64_t *ownStart,
+                                  const int32_t *fnb, int64_t *count, const int64_t *offs,
+                                  int32_t *list) {
+    GRID_STRIDE(c, ncf) {
+        const int32_t a = cown[c], b = cnb[c];
+        int32_t ka = start[a], kb = start[b];
+        const int32_t ea = start[a + 1], eb = start[b + 1];
+        int64_t m = LIST ? offs[c] : 0;
+        while (ka < ea || kb < eb) {
+            int32_t i;
+            bool in_a;
+            if (kb >= eb || (ka < ea && cells[ka] < cells[kb])) { i = cells[ka++]; in_a = true; }
+            else { i = cells[kb++]; in_a = false; }
+            const int32_t other = in_a ? b : a;
+            for (int64_t f = ownStart[i]; f < ownStart[i + 1]; ++f) {
+                if (agg[fnb[f]] != other) continue;
+                if (LIST) list[m] = in_a ? (int32_t)f : ~(int32_t)f;
+                ++m;
+            }
+        }
+        if (!LIST) count[c] = m;
+    }
+}
+template <bool LIST>
+__global__ void k_coarse_celllist(int32_t nc, const int32_t *agg, const int32_t *start,
+                                  const int32_t *cells, const int64_t *ownStart,
+                                  const int32_t *fnb, int64_t *count, const int64_t *offs,
+                                  int32_t *list) {
+    GRID_STRIDE(a, nc) {
+        int64_t m = LIST ? offs[a] : 0;
+        for (int32_t k = start[a]; k < start[a + 1]; ++k) {
+            const int32_t i = cells[k];
+            for (int64_t f = ownStart[i]; f < ownStart[i + 1]; ++f) {
+                if (agg[fnb[f]] != (int32_t)a) continue;
+                if (LIST) list[m] = (int32_t)f;
+                ++m;
+            }
+        }
+        if (!LIST) count[a] = m;
+    }
+}
+
+// coarse values from the recorded lists (the sums of k_coarse_values and
+// k_coarse_diag, term for term)
+__global__ void k_coarse_values_list(int64_t ncf, const int64_t *__restrict__ cfs,
+                                     const int32_t *__restrict__ cff,
+                                     const double *__restrict__ fup,
+                                     const double *__restrict__ flo, double *__restrict__ cup,
+                                     double *__restrict__ clo) {
+    GRID_STRIDE(c, ncf) {
+        double up = 0.0, lo = 0.0;
+        for (int64_t k = cfs[c]; k < cfs[c + 1]; ++k) {
+            const int32_t g = cff[k];
+            if (g >= 0) { up += fup[g]; lo += flo[g]; }
+            else { up += flo[~g]; lo += fup[~g]; }
+        }
+        cup[c] = up;
+        clo[c] = lo;
+    }
+}
+__global__ void k_coarse_diag_list(int32_t nc, const int32_t *__restrict__ start,
+                                   const int32_t *__restrict__ cells,
+                                   const int64_t *__restrict__ cis,
+                                   const int32_t *__restrict__ cif,
+                                   const double *__restrict__ fdiag,
+                                   const double *__restrict__ fup,
+                                   const double *__restrict__ flo, double *__restrict__ cdiag) {
+    GRID_STRIDE(a, nc) {
+        double d = 0.0;
+        for (int32_t k = start[a]; k < start[a + 1]; ++k) d += fdiag[cells[k]];
+        for (int64_t k = cis[a]; k < cis[a + 1]; ++k) {
+            const int32_t f = cif[k];
+            d += (fup[f] + flo[f]);
+        }
+        cdiag[a] = d;
+    }
+}
+
 __global__ void k_coarse_diag(int32_t nc, const int32_t *agg, const int32_t *start,
                               const int32_t *cells, const int64_t *ownStart, const int32_t *fnb,
                               const double *fdiag, const double *fup, const double *flo,
@@ -280,13 +364,56 @@ static void alloc_work(Level &L, Arena &ar) {
 }
 
 static void coarse_values(ldu_t *h, Level &F, Level &C, hipStream_t st) {
-    if (C.nf > 0)
-        k_coarse_values<<<grid_n(C.nf), kBlock, 0, st>>>(C.nf, C.own, C.nb, F.agg, F.aggStart,
-                                                          F.aggCells, F.ownStart, F.nb, F.upper,
-                                                          F.lower, C.upper, C.lower);
-    k_coarse_diag<<<grid_n(C.n), kBlock, 0, st>>>(C.n, F.agg, F.aggStart, F.aggCells, F.ownStart,
-                                                  F.nb, F.diag, F.upper, F.lower, C.diag);
+    if (F.cfStart) {  // recorded visits (hierarchy levels)
+        if (C.nf > 0)
+            k_coarse_values_list<<<grid_n(C.nf), kBlock, 0, st>>>(C.nf, F.cfStart, F.cfFace,
+                                                                   F.upper, F.lower, C.upper,
+                                                                   C.lower);
+        k_coarse_diag_list<<<grid_n(C.n), kBlock, 0, st>>>(C.n, F.aggStart, F.aggCells,
+                                                           F.ciStart, F.ciFace, F.diag, F.upper,
+                                                           F.lower, C.diag);
+    } else {  // the aggressive passes' temporary matrices
+        if (C.nf > 0)
+            k_coarse_values<<<grid_n(C.nf), kBlock, 0, st>>>(C.nf, C.own, C.nb, F.agg,
+                                                              F.aggStart, F.aggCells, F.ownStart,
+                                                              F.nb, F.upper, F.lower, C.upper,
+                                                              C.lower);
+        k_coarse_diag<<<grid_n(C.n), kBlock, 0, st>>>(C.n, F.agg, F.aggStart, F.aggCells,
+                                                      F.ownStart, F.nb, F.diag, F.upper, F.lower,
+                                                      C.diag);
+    }
     HIP_CHECK(hipGetLastError());
+}
+
+// record the fine faces each coarse value and diagonal sums (count, scan, fill)
+static void coarse_lists(Level &F, const Level &C, Arena &ar, hipStream_t st) {
+    Arena tmp;
+    int64_t *cnt = tmp.get<int64_t>((size_t)C.nf + 1);
+    F.cfStart = ar.get<int64_t>((size_t)C.nf + 1);
+    if (C.nf > 0)
+        k_coarse_facelist<false><<<grid_n(C.nf), kBlock, 0, st>>>(
+            C.nf, C.own, C.nb, F.agg, F.aggStart, F.aggCells, F.ownStart, F.nb, cnt, nullptr,
+            nullptr);
+    exclusive_scan_i64(cnt, F.cfStart, C.nf, tmp, st);
+    int64_t *cntc = tmp.get<int64_t>((size_t)C.n + 1);
+    F.ciStart = ar.get<int64_t>((size_t)C.n + 1);
+    k_coarse_celllist<false><<<grid_n(C.n), kBlock, 0, st>>>(
+        C.n, F.agg, F.aggStart, F.aggCells, F.ownStart, F.nb, cntc, nullptr, nullptr);
+    exclusive_scan_i64(cntc, F.ciStart, C.n, tmp, st);
+    int64_t nff = 0, nif = 0;
+    HIP_CHECK(hipMemcpyAsync(&nff, F.cfStart + C.nf, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(&nif, F.ciStart + C.n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    F.cfFace = ar.get<int32_t>((size_t)nff + 1);
+    F.ciFace = ar.get<int32_t>((size_t)nif + 1);
+    if (C.nf > 0)
+        k_coarse_facelist<true><<<grid_n(C.nf), kBlock, 0, st>>>(
+            C.nf, C.own, C.nb, F.agg, F.aggStart, F.aggCells, F.ownStart, F.nb, nullptr,
+            F.cfStart, F.cfFace);
+    k_coarse_celllist<true><<<grid_n(C.n), kBlock, 0, st>>>(
+        C.n, F.agg, F.aggStart, F.aggCells, F.ownStart, F.nb, nullptr, F.ciStart, F.ciFace);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
@@ -418,6 +545,8 @@ void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
     Arena &ar = h->gamg_arena;
     h->levels.push_back(h->L0);
     h->levels[0].agg = h->levels[0].aggStart = h->levels[0].aggCells = nullptr;
+    h->levels[0].cfStart = h->levels[0].ciStart = nullptr;
+    h->levels[0].cfFace = h->levels[0].ciFace = nullptr;
     const int maxl = std::min(std::max(o.max_levels, 1), kMaxLevels);
     while ((int)h->levels.size() < maxl) {
         const size_t l = h->levels.size() - 1;
@@ -430,6 +559,7 @@ void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
         }
         Level C;
         galerkin(h, h->levels[l], C, ar, st);
+        coarse_lists(h->levels[l], C, ar, st);  // for value refreshes on this structure
         build_level_sell(h, ar, C, false, st);
         h->levels.push_back(C);
     }

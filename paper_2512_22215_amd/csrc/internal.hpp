@@ -145,6 +145,11 @@ struct Level {
     // aggregation to the next level (absent on the coarsest level)
     int32_t nc = 0;
     int32_t *agg = nullptr, *aggStart = nullptr, *aggCells = nullptr;
+    // the fine faces each Galerkin sum visits, in its order: per coarse face
+    // (cfStart[ncf+1], cfFace: f if the fine owner lies in the coarse owner,
+    // else ~f), and per coarse cell its internal fine faces (ciStart, ciFace)
+    int64_t *cfStart = nullptr, *ciStart = nullptr;
+    int32_t *cfFace = nullptr, *ciFace = nullptr;
     int singular = 0;                     // coarsest level: A 1 = 0
     int max_row = 0;                      // longest row (off-diagonal entries)
     // V-cycle work vectors

@@ -1322,6 +1322,18 @@ static void gs2_sweep32(const fmat *m, const float *r, float *e, int from_zero,
     for (int32_t i = 0; i < n; ++i) e[i] = from_zero ? g[i] : e[i] + g[i];
 }
 
+void orc_gs2_sweep32(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+                     const float *diag, const float *upper, const float *lower,
+                     const float *r, float *e, int from_zero, int backward,
+                     int inner) {
+    fmat m = {n, nf, own, nb, (float *)diag, (float *)upper, (float *)lower};
+    float *t = xcalloc((size_t)n + 1, sizeof(float));
+    float *g = xcalloc((size_t)n + 1, sizeof(float));
+    float *y = xcalloc((size_t)n + 1, sizeof(float));
+    gs2_sweep32(&m, r, e, from_zero, backward, inner, t, g, y);
+    free(t); free(g); free(y);
+}
+
 static void vcycle32(const orc_gamg *h, int l, const float *r, float *e,
                      const vparams *vp) {
     const olevel *L = &h->lev[l];
@@ -1373,6 +1385,13 @@ static void vcycle32(const orc_gamg *h, int l, const float *r, float *e,
         else jacobi_sweep32(&m, r, e, y, omega);
     }
     free(y); free(t); free(c); free(g); free(rc); free(ec);
+}
+
+int orc_gamg_vcycle32(const orc_gamg *h, const float *r, float *e, int n_pre,
+                      int n_post, double omega, int scale, int transpose) {
+    vparams vp = {n_pre, n_post, scale, transpose, omega};
+    vcycle32(h, 0, r, e, &vp);
+    return ORC_OK;
 }
 
 typedef struct {

@@ -102,6 +102,11 @@ void orc_gs2_sweep(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
                    const double *diag, const double *upper, const double *lower,
                    const double *r, double *e, int from_zero, int backward,
                    int inner);
+/* the same sweep in FP32 (the smoother of the mixed-precision V-cycle) */
+void orc_gs2_sweep32(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
+                     const float *diag, const float *upper, const float *lower,
+                     const float *r, float *e, int from_zero, int backward,
+                     int inner);
 /* DIC pivots Dt (dt may be NULL) and z = M^-1 r (r, z may be NULL); returns 1
  * when every pivot is usable, 0 when the diagonal fallback applies */
 int orc_dic(int32_t n, int64_t nf, const int32_t *own, const int32_t *nb,
@@ -123,6 +128,10 @@ void orc_gamg_level_match(const orc_gamg *h, int level, int32_t *partner,
 /* one V-cycle e = V(0, r) (e is output only) */
 int orc_gamg_vcycle(const orc_gamg *h, const double *r, double *e, int n_pre,
                     int n_post, double omega, int scale, int transpose);
+/* the same V-cycle in FP32 (coarsest level solved in FP64), as the mixed-
+ * precision solvers apply it */
+int orc_gamg_vcycle32(const orc_gamg *h, const float *r, float *e, int n_pre,
+                      int n_post, double omega, int scale, int transpose);
 int orc_gamg_solve(const orc_gamg *h, const double *b, double *x, double tol,
                    int max_cycles, int n_pre, int n_post, double omega,
                    int scale, int transpose, int *cycles, double *hist,

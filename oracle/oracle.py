@@ -86,6 +86,8 @@ def lib():
     L.orc_gamg_set_cycle.argtypes = [vp, C.c_int, C.c_int, C.c_int]
     L.orc_gs2_sweep.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p,
                                 C.c_int, C.c_int, C.c_int]
+    L.orc_gs2_sweep32.argtypes = [i32, i64, _i32p, _i32p, _f32p, _f32p, _f32p, _f32p,
+                                  _f32p, C.c_int, C.c_int, C.c_int]
     L.orc_dic.argtypes = [i32, i64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64o, _f64o, _f64o]
     L.orc_gamg_set_values.argtypes = [vp, _f64p, _f64p, _f64p]
     L.orc_gamg_nlevels.argtypes = [vp]
@@ -95,6 +97,8 @@ def lib():
     L.orc_gamg_level_match.argtypes = [vp, C.c_int, _i32o, _i32o]
     L.orc_gamg_vcycle.argtypes = [vp, _f64p, _f64p, C.c_int, C.c_int, d, C.c_int,
                                   C.c_int]
+    L.orc_gamg_vcycle32.argtypes = [vp, _f32p, _f32p, C.c_int, C.c_int, d, C.c_int,
+                                    C.c_int]
     L.orc_gamg_solve.argtypes = [vp, _f64p, _f64p, d, C.c_int, C.c_int, C.c_int, d,
                                  C.c_int, C.c_int, ip, _f64o, dp]
     L.orc_pcg_gamg.argtypes = [vp, _f64p, _f64p, d, C.c_int, C.c_int, C.c_int, d,
@@ -290,6 +294,15 @@ class Gamg:
                               int(bool(transpose)))
         return e
 
+    def vcycle_f32(self, r, n_pre=2, n_post=2, omega=0.75, scale=True,
+                   transpose=False):
+        """The FP32 V-cycle of the mixed-precision solvers."""
+        e = np.zeros(self.A.n, np.float32)
+        lib().orc_gamg_vcycle32(self._h, _c(r, np.float32), e, int(n_pre),
+                                int(n_post), float(omega), int(bool(scale)),
+                                int(bool(transpose)))
+        return e
+
     def solve(self, b, x0=None, tol=1e-8, max_cycles=200, n_pre=2, n_post=2,
               omega=0.75, scale=True, transpose=False):
         x = np.zeros(self.A.n) if x0 is None else _c(x0, np.float64).copy()
@@ -361,6 +374,17 @@ def gs2_sweep(A: Ldu, r, e=None, backward=False, inner=1):
     out = np.zeros(A.n) if e is None else _c(e, np.float64).copy()
     lib().orc_gs2_sweep(*A.args(), _c(r, np.float64), out, int(e is None),
                         int(bool(backward)), int(inner))
+    return out
+
+
+def gs2_sweep_f32(A: Ldu, r, e=None, backward=False, inner=1):
+    """The FP32 two-stage Gauss-Seidel sweep of the mixed-precision V-cycle
+    (coefficients and vectors rounded to FP32)."""
+    out = np.zeros(A.n, np.float32) if e is None else _c(e, np.float32).copy()
+    lib().orc_gs2_sweep32(A.n, A.nf, A.own, A.nb, A.diag.astype(np.float32),
+                          A.upper.astype(np.float32), A.lower.astype(np.float32),
+                          _c(r, np.float32), out, int(e is None), int(bool(backward)),
+                          int(inner))
     return out
 
 

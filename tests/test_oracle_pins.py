@@ -679,11 +679,71 @@ def test_gs2_unstructured_limit_and_one_step_bound():
     ref = solve_triangular(Dg + L, r, lower=True)
     got = O.gs2_sweep(A, r, inner=c.n_cells)
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    # backward sweeps solve with D + U; the coefficients are nonsymmetric, so
+    # taking the lower ones here would be caught
+    bref = solve_triangular(Dg + U, r, lower=False)
+    bgot = O.gs2_sweep(A, r, backward=True, inner=c.n_cells)
+    assert np.linalg.norm(bgot - bref) <= 1e-12 * np.linalg.norm(bref)
     # one inner step: the error of the triangular solve is (D^-1 L)^2 applied
     # to the exact answer, so it is bounded by ||D^-1 L||^2 ||ref||
     one = O.gs2_sweep(A, r, inner=1)
     K = np.linalg.norm(np.linalg.solve(Dg, L), 2)
     assert np.linalg.norm(one - ref) <= K ** 2 * np.linalg.norm(ref) * (1 + 1e-12)
+
+
+def test_gs2_fp32_sweep_is_the_fp64_sweep_to_fp32_rounding():
+    """The mixed-precision smoother: on FP32-representable data, each inner
+    step of the FP32 sweep rounds a row sum of at most 7 terms and one
+    division, and the steps contract (diagonally dominant rows), so it agrees
+    with the FP64 sweep to a few hundred FP32 units; a wrong operand or sign
+    moves it by O(1)."""
+    c = _perm_case(box_case(6, 5, 4, coeff="lognormal", nonsym=0.4, dirichlet_x0=1.0,
+                            seed=57), 58)
+    A = O.Ldu.from_case(c)
+    A32 = O.Ldu(c.n_cells, c.owner, c.neighbour,
+                *(v.astype(np.float32).astype(np.float64) for v in (A.diag, A.upper,
+                                                                    A.lower)))
+    rng = np.random.default_rng(59)
+    r = rng.standard_normal(c.n_cells).astype(np.float32)
+    e0 = rng.standard_normal(c.n_cells).astype(np.float32)
+    eps = np.finfo(np.float32).eps
+    for backward in (False, True):
+        for inner in (1, 3):
+            for e in (None, e0):
+                want = O.gs2_sweep(A32, r.astype(np.float64),
+                                   None if e is None else e.astype(np.float64),
+                                   backward=backward, inner=inner)
+                got = O.gs2_sweep_f32(A32, r, e, backward=backward, inner=inner)
+                assert got.dtype == np.float32
+                err = np.linalg.norm(got - want) / np.linalg.norm(want)
+                assert err <= 300 * eps, (backward, inner, e is None, err)
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "gs2"])
+def test_fp32_vcycle_is_the_fp64_vcycle_to_fp32_rounding(smoother):
+    """The mixed-precision V-cycle is the FP64 V-cycle (pinned to dense
+    formulas above) with FP32 arithmetic: on FP32-representable coefficients
+    and residual, with the coarsest level solved in FP64 to 1e-10, the two
+    agree to FP32 rounding (measured about 1e-7), forward and transposed,
+    with and without the correction scaling.  A swapped sweep direction or a
+    wrong operand anywhere in the FP32 cycle moves the result by O(1)."""
+    c = _perm_case(box_case(7, 6, 5, coeff="lognormal", nonsym=0.4, dirichlet_x0=1.0,
+                            seed=61), 62)
+    A = O.Ldu.from_case(c)
+    A32 = O.Ldu(c.n_cells, c.owner, c.neighbour,
+                *(v.astype(np.float32).astype(np.float64) for v in (A.diag, A.upper,
+                                                                    A.lower)))
+    g = O.Gamg(A32, n_coarsest=4, smoother=smoother, gs_inner=2)
+    assert g.n_levels >= 4
+    r = np.random.default_rng(63).standard_normal(c.n_cells).astype(np.float32)
+    eps = np.finfo(np.float32).eps
+    for scale in (False, True):
+        for tr in (False, True):
+            want = g.vcycle(r.astype(np.float64), n_pre=2, n_post=2, scale=scale,
+                            transpose=tr)
+            got = g.vcycle_f32(r, n_pre=2, n_post=2, scale=scale, transpose=tr)
+            err = np.linalg.norm(got - want) / np.linalg.norm(want)
+            assert err <= 100 * eps, (scale, tr, err)
 
 
 def test_vcycle_gs2_two_level_dense_formula():
@@ -870,6 +930,11 @@ def test_assembly_column_sums_divergence_and_interpolation():
     assert np.allclose(A.sum(0), -g["diag_bc"], rtol=0, atol=1e-13 * np.abs(d).max())
     # divergence telescopes: interior fluxes cancel in the total
     assert abs(b.sum() - g["b_bc"].sum()) <= 1e-14 * np.abs(g["phi"]).sum()
+    # the boundary source is added to the divergence cell by cell
+    bbc = np.random.default_rng(60).standard_normal(N)
+    _, _, _, b2 = O.assemble_pressure(N, own, nb, g["gamma"], g["weights"], g["mag_sf"],
+                                      g["delta"], g["diag_bc"], g["phi"], bbc)
+    assert np.allclose(b2 - b, bbc - g["b_bc"], rtol=0, atol=1e-14 * np.abs(b).max())
     # a uniform flux through x faces only leaves sources on the x = 0 / x = end layers
     phi_x = np.where(own + 1 == nb, 1.0, 0.0)
     _, _, _, bx = O.assemble_pressure(N, own, nb, g["gamma"], g["weights"], g["mag_sf"],

@@ -217,6 +217,14 @@ int gamg_level_size(ldu_handle h, int level, int64_t *n_cells,
 int gamg_level_export(ldu_handle h, int level, int32_t *agg, int32_t *owner,
                       int32_t *neighbour, double *diag, double *upper,
                       double *lower, void *hip_stream);
+/* Storage of level l's matrix in the product kernels (level 0 needs no GAMG
+ * hierarchy; HOST outputs, either may be NULL).  compressed: 1 when the rows
+ * sit in length-sorted compressed slices, 0 in plain slices of 64 rows.
+ * col16: 1 when the kernels read each column as a 16-bit offset from the
+ * smallest column of its slot (possible when every slot, the k-th entries of
+ * a slice's rows, spans at most 65535 columns), 0 when they read 32-bit
+ * columns.  Either way the products are the same bit for bit. */
+int ldu_level_layout(ldu_handle h, int level, int *compressed, int *col16);
 
 /* Adjoint solve A^T lambda = g on the transposed coefficients (upper and
  * lower exchanged on every level) with solver 0: PCG (opts is an

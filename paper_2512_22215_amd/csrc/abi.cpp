@@ -384,6 +384,17 @@ int gamg_level_size(ldu_handle h, int level, int64_t *n_cells, int64_t *n_faces)
     return LDU_OK;
 }
 
+int ldu_level_layout(ldu_handle h, int level, int *compressed, int *col16) {
+    if (!h) return fail(LDU_ERR_ARG, "NULL handle");
+    if (level < 0) return fail(LDU_ERR_ARG, "bad level");
+    if (level > 0 && !h->gamg_ready) return fail(LDU_ERR_STATE, "GAMG hierarchy not set up");
+    if (level > 0 && level >= (int)h->levels.size()) return fail(LDU_ERR_ARG, "bad level");
+    const Level &L = level == 0 ? h->L0 : h->levels[level];
+    if (compressed) *compressed = L.A.pdeg != nullptr;
+    if (col16) *col16 = L.A.c16 != nullptr;
+    return LDU_OK;
+}
+
 int gamg_level_export(ldu_handle h, int level, int32_t *agg, int32_t *owner, int32_t *neighbour,
                       double *diag, double *upper, double *lower, void *hip_stream) {
     if (!h) return fail(LDU_ERR_ARG, "NULL handle");

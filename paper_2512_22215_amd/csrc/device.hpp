@@ -20,9 +20,13 @@
 
 namespace ldu {
 
-template <class F>
+template <int CAP = 0, class F>
 __device__ __forceinline__ void for_each_slice(int64_t S, F &&f) {
-    const int G = gridDim.x;
+    int G = gridDim.x;
+    if (CAP > 0 && G > CAP) {  // only the first CAP blocks walk slices
+        if ((int)blockIdx.x >= CAP) return;
+        G = CAP;
+    }
     const int nx = (G >= 64 && (G & 7) == 0) ? 8 : 1;
     const int64_t x = blockIdx.x % nx;
     const int64_t j = blockIdx.x / nx;
@@ -35,6 +39,13 @@ __device__ __forceinline__ void for_each_slice(int64_t S, F &&f) {
         const int64_t s = lo + g * kWavesPerBlock + w;
         if (s < hi) f(s);
     }
+}
+
+// active-block cap of a product kernel over level matrix A (see
+// kPlainF64ProductBlocks); 0: every block walks slices
+template <bool CMP, typename T>
+constexpr int product_cap() {
+    return (!CMP && sizeof(T) == 8) ? kPlainF64ProductBlocks : 0;
 }
 
 // Wavefront reductions with DPP lane moves (no LDS round trips): pairs and
@@ -160,32 +171,101 @@ struct ViaAgg {  // prolonged vector c_j = ec[agg[j]]
     __device__ __forceinline__ T operator()(int32_t j) const { return ec[agg[j]]; }
 };
 
-// (A x)_i for the row i stored at position 64 s + lane of slice s; CMP
-// selects the compressed-slice layout at compile time (each layout gets its
-// own kernels, so the plain one keeps its register budget and occupancy)
-template <bool CMP, typename T, class XA>
-__device__ __forceinline__ T sell_row(const SellView<T> &A, int64_t s, int lane,
-                                      int32_t i, const XA &xa) {
+// Offsets of a compressed slice's entries.  Rows are sorted by length
+// within the slice (longest first), so the entries of column k are those of
+// the first cnt_k lanes, cnt_k = #{lanes with length > k}, stored after the
+// entries of columns 0..k-1.  A wave that holds the whole slice (every lane
+// with entries active) counts cnt_k with a ballot and keeps the running
+// offset in a scalar register: no offset table loads on the dependent path
+// from the slice header to the gathers.  Row-per-lane callers, whose lanes
+// belong to different slices, read the slice's offset table instead (TABLE).
+struct SliceOffsets {
+    int64_t off = 0;
+    __device__ __forceinline__ int64_t next(bool has) {
+        const int64_t o = off;
+        off += __popcll(__ballot(has));
+        return o;
+    }
+};
+
+// A wave's walk over the slots of a plain slice s (slot k: the k-th entries
+// of the slice's rows; the slot count is the slice width, wave-uniform, so
+// the slot bases come from scalar loads).  C16: columns are the slot base
+// plus a 16-bit offset.
+template <bool C16, typename T>
+struct PlainWalk {
+    const int32_t *cp;
+    const uint16_t *hp;
+    const T *vp;
+    const int32_t *bp;
+    int w;
+
+    __device__ __forceinline__ PlainWalk(const SellView<T> &A, int64_t s, int lane) {
+        const int64_t b0 = A.sptr[s];
+        cp = A.col + b0 + lane;
+        hp = C16 ? A.c16 + b0 + lane : nullptr;
+        vp = A.val + b0 + lane;
+        w = (int)((A.sptr[s + 1] - b0) >> 6);
+        bp = C16 ? A.cbase + (b0 >> 6) : nullptr;
+    }
+    // stored column (16-bit offset or 32-bit column), slot base and value of
+    // slot k; the column is formed later (column()), so that the vector
+    // loads of a whole batch are in flight before the first wait on them.
+    // The base is a scalar load per slot: those of one slice share a scalar
+    // cache line.  (Reading a fixed batch of bases per step instead measured
+    // slower, with more HBM traffic.)
+    __device__ __forceinline__ void load(int k, int32_t &raw, int32_t &base, T &v) const {
+        const int64_t o = (int64_t)k * kWave;
+        base = C16 ? bp[k] : 0;
+        if constexpr (C16) raw = (int32_t)__builtin_nontemporal_load(hp + o);
+        else raw = __builtin_nontemporal_load(cp + o);
+        v = __builtin_nontemporal_load(vp + o);
+    }
+    static __device__ __forceinline__ int32_t column(int32_t raw, int32_t base) {
+        return C16 ? base + raw : raw;
+    }
+};
+
+template <bool C16, int B, typename T, class XA, class F>
+__device__ __forceinline__ void plain_entries(const SellView<T> &A, int64_t s, int lane,
+                                              const XA &xa, F &&f) {
+    const PlainWalk<C16, T> pw(A, s, lane);
+    for (int k = 0; k < pw.w; k += B) {
+        int32_t c[B], cb[B];
+        T v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (k + u < pw.w) pw.load(k + u, c[u], cb[u], v[u]);
+        T xv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (k + u < pw.w) {
+                c[u] = PlainWalk<C16, T>::column(c[u], cb[u]);
+                xv[u] = xa(c[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (k + u < pw.w) f(c[u], v[u], xv[u]);
+    }
+}
+
+template <int B, typename T, class XA, class F>
+__device__ __forceinline__ void cmp_entries(const SellView<T> &A, int64_t s, int lane,
+                                            const XA &xa, F &&f) {
     const int64_t b0 = A.sptr[s];
-    T acc = A.diag[i] * xa(i);
     const int32_t *cp = A.col + b0 + lane;
     const T *vp = A.val + b0 + lane;
-    int w;
-    const int32_t *ot = nullptr;
-    if constexpr (CMP) {
-        w = A.pdeg[s * kWave + lane];
-        ot = A.otab + A.tptr[s];
-    } else {
-        w = (int)((A.sptr[s + 1] - b0) >> 6);
-    }
-    constexpr int B = CMP ? kCmpBatch : 8;  // entries loaded per batch
+    const int w = A.pdeg[s * kWave + lane];
+    SliceOffsets so;
     for (int k = 0; k < w; k += B) {
         int32_t c[B];
         T v[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            if (k + u < w) {
-                const int64_t o = CMP ? (int64_t)ot[k + u] : (int64_t)(k + u) * kWave;
+            const bool has = k + u < w;
+            const int64_t o = so.next(has);
+            if (has) {
                 c[u] = __builtin_nontemporal_load(cp + o);
                 v[u] = __builtin_nontemporal_load(vp + o);
             }
@@ -196,56 +276,82 @@ __device__ __forceinline__ T sell_row(const SellView<T> &A, int64_t s, int lane,
             if (k + u < w) xv[u] = xa(c[u]);
 #pragma unroll
         for (int u = 0; u < B; ++u)
-            if (k + u < w) acc = acc + v[u] * xv[u];
+            if (k + u < w) f(c[u], v[u], xv[u]);
     }
-    return acc;
+}
+
+// the off-diagonal entries of the row at slice position 64 s + lane, loaded
+// B at a time: f(column, value, x[column]) for each, in column order.  Plain
+// slices walk their slots with PlainWalk; compressed slices loop per lane to
+// the row's own length, with ballot-counted offsets.
+template <bool CMP, int B, typename T, class XA, class F>
+__device__ __forceinline__ void row_entries(const SellView<T> &A, int64_t s, int lane,
+                                            const XA &xa, F &&f) {
+    if constexpr (CMP) {
+        cmp_entries<B>(A, s, lane, xa, f);
+    } else {
+        if (A.c16) plain_entries<true, B>(A, s, lane, xa, f);
+        else plain_entries<false, B>(A, s, lane, xa, f);
+    }
+}
+
+// (A x)_i for the row i stored at position 64 s + lane of slice s; CMP
+// selects the compressed-slice layout at compile time (each layout gets its
+// own kernels, so the plain one keeps its register budget and occupancy).
+// Without TABLE every lane of the slice that holds a row must be active;
+// TABLE serves row-per-lane callers (lanes in different slices) from the
+// 32-bit columns and the offset table.
+template <bool CMP, typename T, class XA, bool TABLE = false>
+__device__ __forceinline__ T sell_row(const SellView<T> &A, int64_t s, int lane,
+                                      int32_t i, const XA &xa) {
+    if constexpr (!TABLE) {
+        T acc = A.diag[i] * xa(i);
+        row_entries<CMP, CMP ? kCmpBatch : 8>(A, s, lane, xa, [&](int32_t, T v, T xv) {
+            acc = acc + v * xv;
+        });
+        return acc;
+    } else {
+        const int64_t b0 = A.sptr[s];
+        T acc = A.diag[i] * xa(i);
+        const int32_t *cp = A.col + b0 + lane;
+        const T *vp = A.val + b0 + lane;
+        int w;
+        const int32_t *ot = nullptr;
+        if constexpr (CMP) {
+            w = A.pdeg[s * kWave + lane];
+            ot = A.otab + A.tptr[s];
+        } else {
+            w = (int)((A.sptr[s + 1] - b0) >> 6);
+        }
+        for (int k = 0; k < w; ++k) {
+            const int64_t o = CMP ? (int64_t)ot[k] : (int64_t)k * kWave;
+            acc = acc + vp[o] * xa(cp[o]);
+        }
+        return acc;
+    }
 }
 
 // strictly lower (UPPER false: columns < i) or strictly upper (columns > i)
 // part of row i applied to x, summed from zero in column order; padding
-// entries (column == i) drop out with the mask
+// entries (column == i) drop out with the mask.  Every lane of the slice
+// that holds a row must be active.
 template <bool CMP, bool UPPER, typename T, class XA>
 __device__ __forceinline__ T sell_tri(const SellView<T> &A, int64_t s, int lane, int32_t i,
                                       const XA &xa) {
-    const int64_t b0 = A.sptr[s];
     T acc = T(0);
-    const int32_t *cp = A.col + b0 + lane;
-    const T *vp = A.val + b0 + lane;
-    int w;
-    const int32_t *ot = nullptr;
-    if constexpr (CMP) {
-        w = A.pdeg[s * kWave + lane];
-        ot = A.otab + A.tptr[s];
-    } else {
-        w = (int)((A.sptr[s + 1] - b0) >> 6);
-    }
-    for (int k = 0; k < w; k += 8) {
-        int32_t c[8];
-        T v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (k + u < w) {
-                const int64_t o = CMP ? (int64_t)ot[k + u] : (int64_t)(k + u) * kWave;
-                c[u] = __builtin_nontemporal_load(cp + o);
-                v[u] = __builtin_nontemporal_load(vp + o);
-            }
-        }
-        T xv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (k + u < w) xv[u] = xa(c[u]);
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (k + u < w && (UPPER ? c[u] > i : c[u] < i)) acc = acc + v[u] * xv[u];
-    }
+    row_entries<CMP, 8>(A, s, lane, xa, [&](int32_t c, T v, T xv) {
+        if (UPPER ? c > i : c < i) acc = acc + v * xv;
+    });
     return acc;
 }
 
-// either layout, decided at run time (small levels and setup kernels)
+// either layout, decided at run time, for row-per-lane callers (setup
+// kernels, the block coarsest solve)
 template <typename T, class XA>
 __device__ __forceinline__ T sell_row_any(const SellView<T> &A, int64_t s, int lane, int32_t i,
                                           const XA &xa) {
-    return A.pdeg ? sell_row<true>(A, s, lane, i, xa) : sell_row<false>(A, s, lane, i, xa);
+    return A.pdeg ? sell_row<true, T, XA, true>(A, s, lane, i, xa)
+                  : sell_row<false, T, XA, true>(A, s, lane, i, xa);
 }
 
 // entry count of the row at slice position p, and the storage index of its

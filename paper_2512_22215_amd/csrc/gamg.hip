@@ -681,7 +681,7 @@ k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
     if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
-    for_each_slice(A.nslices, [&](int64_t s) {
+    for_each_slice<product_cap<CMP, T>()>(A.nslices, [&](int64_t s) {
         const int64_t p = s * kWave + lane;
         if (p < A.n) {
             const int32_t i = sv_row<CMP>(A, p);
@@ -702,7 +702,7 @@ k_vc_resid(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
            T *__restrict__ t, const DevScalars *ds) {
     if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
-    for_each_slice(A.nslices, [&](int64_t s) {
+    for_each_slice<product_cap<CMP, T>()>(A.nslices, [&](int64_t s) {
         const int64_t p = s * kWave + lane;
         if (p < A.n) {
             const int32_t i = sv_row<CMP>(A, p);
@@ -730,7 +730,7 @@ k_vc_gs(SellView<T> A, const T *__restrict__ t, const T *__restrict__ g, T *__re
         int mode, const DevScalars *ds) {
     if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
-    for_each_slice(A.nslices, [&](int64_t s) {
+    for_each_slice<product_cap<CMP, T>()>(A.nslices, [&](int64_t s) {
         const int64_t p = s * kWave + lane;
         if (p < A.n) {
             const int32_t i = sv_row<CMP>(A, p);
@@ -767,7 +767,7 @@ k_vc_scale(SellView<T> A, const T *__restrict__ ec, const int32_t *__restrict__ 
     if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     double acc[2] = {0.0, 0.0};
-    for_each_slice(A.nslices, [&](int64_t s) {
+    for_each_slice<product_cap<CMP, T>()>(A.nslices, [&](int64_t s) {
         const int64_t p = s * kWave + lane;
         if (p < A.n) {
             const int32_t i = sv_row<CMP>(A, p);

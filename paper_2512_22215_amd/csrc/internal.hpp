@@ -19,6 +19,14 @@
 //    otab[tptr[s] + k] counts the entries of the slice's first k columns.
 //    Nothing is padded, and a row's loads and stores stay inside the slice's
 //    own cache lines.
+//  - 16-bit columns: for each stored column k of a slice (a "slot": the k-th
+//    entries of the slice's rows), cbase holds the smallest column of the
+//    slot and c16 each entry's column minus that base.  Levels whose slots
+//    all span at most 65535 columns use them in the product kernels (2 bytes
+//    per entry instead of 4, and a shorter stream between the reuses of x);
+//    the others keep c16 = NULL and read the 32-bit columns.  The slot of
+//    (s, k) is (sptr[s] / 64) + k in plain slices and tptr[s] + k in
+//    compressed ones.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,6 +44,11 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxGrid = 2048;     // streaming kernels: at most this many blocks
+// FP64 products on plain slices: at most this many blocks walk slices (the
+// rest only contribute zero partials).  Four waves per SIMD instead of eight
+// keep fewer of the streamed matrix lines in flight, so more of x survives
+// in L2 between its reuses one mesh plane apart.
+constexpr int kPlainF64ProductBlocks = 1024;
 #ifndef LDU_CMP_BATCH
 #define LDU_CMP_BATCH 16
 #endif
@@ -76,6 +89,8 @@ struct SellView {
     const int32_t *pdeg;   // compressed slices: entries of the row at position p
     const int32_t *tptr;   // compressed slices: start of slice s in otab
     const int32_t *otab;   // compressed slices: offset of entry k within slice s
+    const uint16_t *c16;   // column minus its slot base (NULL: use col)
+    const int32_t *cbase;  // smallest column of each slot
 };
 
 // scalars shared between the kernels of one solve; device resident
@@ -124,13 +139,17 @@ struct Sell {
     float *diag32 = nullptr;
     // compressed slices (levels with uneven rows): lanes sorted by row length
     int32_t *perm = nullptr, *iperm = nullptr, *pdeg = nullptr, *tptr = nullptr, *otab = nullptr;
+    // 16-bit column offsets and slot bases (c16 NULL when some slot is too wide)
+    uint16_t *c16 = nullptr;
+    int32_t *cbase = nullptr;
 
     __host__ __device__ SellView<double> view(bool transpose) const {
-        return {n, nslices, sptr, col, transpose ? valT : val, diag, perm, iperm, pdeg, tptr, otab};
+        return {n,    nslices, sptr, col,  transpose ? valT : val, diag, perm, iperm, pdeg,
+                tptr, otab,    c16,  cbase};
     }
     __host__ __device__ SellView<float> view32(bool transpose) const {
-        return {n, nslices, sptr, col, transpose ? valT32 : val32, diag32, perm, iperm, pdeg,
-                tptr, otab};
+        return {n,    nslices, sptr, col,  transpose ? valT32 : val32, diag32, perm, iperm, pdeg,
+                tptr, otab,    c16,  cbase};
     }
 };
 

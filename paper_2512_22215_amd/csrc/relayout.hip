@@ -350,6 +350,84 @@ __global__ void k_set_values(int64_t nf, const int64_t *slotU, const int64_t *sl
     }
 }
 
+// slot bases for 16-bit columns: the smallest column of each slot, and a
+// flag when some slot spans more than 65535 columns
+__device__ __forceinline__ void slot_span(const int64_t *sptr, const int32_t *pdeg,
+                                          const int32_t *tptr, const int32_t *otab, int64_t s,
+                                          int k, int64_t &e0, int &cnt, int64_t &bi) {
+    if (pdeg) {
+        const int32_t *ot = otab + tptr[s];
+        e0 = sptr[s] + ot[k];
+        cnt = ot[k + 1] - ot[k];
+        bi = tptr[s] + k;
+    } else {
+        e0 = sptr[s] + (int64_t)k * kWave;
+        cnt = kWave;
+        bi = (sptr[s] >> 6) + k;
+    }
+}
+
+__global__ void k_col16_bases(int64_t S, const int64_t *sptr, const int32_t *pdeg,
+                              const int32_t *tptr, const int32_t *otab, const int32_t *col,
+                              int32_t *cbase, int *wide) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int w = pdeg ? pdeg[s * kWave] : (int)((sptr[s + 1] - sptr[s]) >> 6);
+        for (int k = 0; k < w; ++k) {
+            int64_t e0, bi;
+            int cnt;
+            slot_span(sptr, pdeg, tptr, otab, s, k, e0, cnt, bi);
+            int32_t lo = col[e0], hi = col[e0];
+            for (int l = 1; l < cnt; ++l) {
+                const int32_t c = col[e0 + l];
+                lo = c < lo ? c : lo;
+                hi = c > hi ? c : hi;
+            }
+            cbase[bi] = lo;
+            if ((int64_t)hi - lo > 65535) atomicOr(wide, 1);
+        }
+    }
+}
+
+__global__ void k_col16_fill(int64_t S, const int64_t *sptr, const int32_t *pdeg,
+                             const int32_t *tptr, const int32_t *otab, const int32_t *col,
+                             const int32_t *cbase, uint16_t *c16) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int w = pdeg ? pdeg[s * kWave] : (int)((sptr[s + 1] - sptr[s]) >> 6);
+        for (int k = 0; k < w; ++k) {
+            int64_t e0, bi;
+            int cnt;
+            slot_span(sptr, pdeg, tptr, otab, s, k, e0, cnt, bi);
+            for (int l = 0; l < cnt; ++l) c16[e0 + l] = (uint16_t)(col[e0 + l] - cbase[bi]);
+        }
+    }
+}
+
+// 16-bit columns for a level whose slots are all narrow enough
+static void build_col16(Sell &A, int64_t nslots, Arena &ar, Arena &tmp, hipStream_t st) {
+    A.c16 = nullptr;
+    A.cbase = nullptr;
+    // plain slices only: in compressed slices the slot bases cost more than
+    // the narrower columns save (measured on the Galerkin levels)
+    if (A.nnz == 0 || nslots == 0 || A.pdeg) return;
+    int32_t *cbase = ar.get<int32_t>(nslots);
+    int *wide = tmp.get<int>(1);
+    k_fill_i32<<<1, kBlock, 0, st>>>(wide, 1, 0);
+    k_col16_bases<<<grid_for(A.nslices), kBlock, 0, st>>>(A.nslices, A.sptr, A.pdeg, A.tptr,
+                                                         A.otab, A.col, cbase, wide);
+    int hwide = 1;
+    HIP_CHECK(hipMemcpyAsync(&hwide, wide, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (hwide) return;
+    uint16_t *c16 = ar.get<uint16_t>(A.nnz);
+    k_col16_fill<<<grid_for(A.nslices), kBlock, 0, st>>>(A.nslices, A.sptr, A.pdeg, A.tptr,
+                                                        A.otab, A.col, cbase, c16);
+    HIP_CHECK(hipGetLastError());
+    A.c16 = c16;
+    A.cbase = cbase;
+}
+
 __global__ void k_to_f32(const double *a, float *b, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -388,6 +466,7 @@ void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t 
     HIP_CHECK(hipMemcpyAsync(&nnz, L.A.sptr + S, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     L.A.perm = L.A.iperm = L.A.pdeg = L.A.tptr = L.A.otab = nullptr;
+    int64_t nslots = nnz / kWave;  // plain slices: one slot per 64 entries
     if (nnz * 100 > 103 * std::max<int64_t>(2 * nf, kWave)) {
         // rows of uneven length: compressed slices, lanes ordered by length
         L.A.perm = ar.get<int32_t>(S * kWave);
@@ -407,6 +486,7 @@ void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t 
                                  st));
         HIP_CHECK(hipStreamSynchronize(st));
         L.A.otab = ar.get<int32_t>(ntab);
+        nslots = ntab;
         k_slice_table<<<grid_for(S), kBlock, 0, st>>>(S, L.A.pdeg, L.A.tptr, L.A.otab);
     }
     {  // longest row, for kernels that stage a whole row
@@ -440,6 +520,7 @@ void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t 
         k_fill_pad<<<grid_for(S * kWave), kBlock, 0, st>>>(n, S, L.A.sptr, deg, L.A.col, L.A.val,
                                                           L.A.valT);
     HIP_CHECK(hipGetLastError());
+    build_col16(L.A, nslots, ar, tmp, st);
     set_level_values(L, st);
     HIP_CHECK(hipStreamSynchronize(st));  // tmp is released after this point
 }

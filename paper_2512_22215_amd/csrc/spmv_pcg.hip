@@ -23,7 +23,7 @@ template <bool CMP, typename T>
 __global__ void __launch_bounds__(kBlock) k_amul(SellView<T> A, const T *__restrict__ x,
                                                  T *__restrict__ y) {
     const int lane = threadIdx.x & 63;
-    for_each_slice(A.nslices, [&](int64_t s) {
+    for_each_slice<product_cap<CMP, T>()>(A.nslices, [&](int64_t s) {
         const int64_t p = s * kWave + lane;
         if (p < A.n) {
             const int32_t i = sv_row<CMP>(A, p);
@@ -101,7 +101,7 @@ k_residual(SellView<double> A, const double *__restrict__ b, const double *__res
     if (gated && ds->done) return;
     const int lane = threadIdx.x & 63;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // rr, bb, rho, maxabs
-    for_each_slice(A.nslices, [&](int64_t s) {
+    for_each_slice<product_cap<CMP, double>()>(A.nslices, [&](int64_t s) {
         const int64_t pos = s * kWave + lane;
         if (pos < A.n) {
             const int32_t i = sv_row<CMP>(A, pos);
@@ -201,7 +201,7 @@ k_pcg_q(SellView<double> A, const double *__restrict__ p, double *__restrict__ q
     if (ds->done) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
-    for_each_slice(A.nslices, [&](int64_t s) {
+    for_each_slice<product_cap<CMP, double>()>(A.nslices, [&](int64_t s) {
         const int64_t pos = s * kWave + lane;
         if (pos < A.n) {
             const int32_t i = sv_row<CMP>(A, pos);
@@ -429,7 +429,7 @@ k_bicg_q(SellView<double> A, const double *__restrict__ valT, const double *__re
     At.val = valT;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
-    for_each_slice(A.nslices, [&](int64_t s) {
+    for_each_slice<product_cap<CMP, double>()>(A.nslices, [&](int64_t s) {
         const int64_t pos = s * kWave + lane;
         if (pos < A.n) {
             const int32_t i = sv_row<CMP>(A, pos);

@@ -25,7 +25,7 @@ EXPORTED = (
     "ldu_pcg_default_opts", "ldu_gamg_default_opts", "ldu_create", "ldu_set_coeffs",
     "ldu_destroy", "ldu_amul", "ldu_tmul", "ldu_amul_f32", "ldu_residual", "pcg_solve",
     "pbicg_solve", "gamg_setup", "gamg_solve", "gamg_vcycle", "gamg_level_size", "gamg_level_export",
-    "ldu_adjoint_solve", "ldu_coeff_grad", "ldu_assemble_pressure", "ldu_last_error",
+    "ldu_level_layout", "ldu_adjoint_solve", "ldu_coeff_grad", "ldu_assemble_pressure", "ldu_last_error",
 )
 
 
@@ -102,6 +102,7 @@ def lib():
     L.gamg_vcycle.argtypes = [vp, vp, vp, C.POINTER(GamgOpts), vp]
     L.gamg_level_size.argtypes = [vp, i, C.POINTER(i64), C.POINTER(i64)]
     L.gamg_level_export.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp]
+    L.ldu_level_layout.argtypes = [vp, i, C.POINTER(i), C.POINTER(i)]
     L.ldu_adjoint_solve.argtypes = [vp, vp, vp, i, vp, C.POINTER(Stats), vp]
     L.ldu_coeff_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.ldu_assemble_pressure.argtypes = [vp] * 13
@@ -302,6 +303,12 @@ class LduMatrix:
                                        _ptr(out["upper"]), _ptr(out["lower"]), _stream()),
                False)
         return out
+
+    def layout(self, l=0):
+        """Storage of level l in the product kernels: {"compressed", "col16"}."""
+        cmp_, c16 = C.c_int(), C.c_int()
+        _check(lib().ldu_level_layout(self._h, l, C.byref(cmp_), C.byref(c16)), False)
+        return {"compressed": bool(cmp_.value), "col16": bool(c16.value)}
 
     def adjoint(self, g, use_gamg=False, x0=None, history=0, solver=None, **kw):
         """A^T lambda = g; solver "pcg" (default), "gamg" (or use_gamg=True) or

@@ -34,6 +34,7 @@ def c3():
 def test_c3_amul_and_level0_hierarchy_bit_exact(c3):
     from paper_2512_22215_amd import LduMatrix
     m = LduMatrix.from_case(c3)
+    assert m.layout(0) == {"compressed": False, "col16": True}
     A = O.Ldu.from_case(c3)
     x = np.random.default_rng(7).standard_normal(c3.n_cells)
     assert np.array_equal(m.amul(_t(x)).cpu().numpy(), O.amul(A, x))

@@ -538,6 +538,8 @@ static void galerkin(ldu_t *h, Level &F, Level &C, Arena &ar, hipStream_t st) {
     HIP_CHECK(hipStreamSynchronize(st));
 }
 
+static void ensure_rop(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st);
+
 void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
     h->gamg_ready = false;
     h->levels.clear();
@@ -577,6 +579,14 @@ void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
     detect_singular(h, h->levels.back(), st);
     h->gamg_opts = o;
     h->gamg_ready = true;
+    // a Jacobi cycle with one pre-sweep will run its down leg through R (the
+    // CG + V-cycle solve turns correction scaling off): build it with the
+    // hierarchy
+    if (o.smoother == LDU_SMOOTH_JACOBI && o.n_pre == 1) {
+        ldu_gamg_opts q = o;
+        q.scale_correction = 0;
+        ensure_rop(h, q, st);
+    }
 }
 
 // new level-0 values: recompute every coarse matrix on the cached structure
@@ -591,6 +601,7 @@ void gamg_refresh_values(ldu_t *h, hipStream_t st) {
     }
     detect_singular(h, h->levels.back(), st);
     h->dic_ready = false;
+    for (auto &L : h->levels) L.r_ready = false;
 }
 
 // DIC pivots of the coarsest level (diagonal incomplete Cholesky; the paper's
@@ -757,6 +768,165 @@ k_vc_restrict(int32_t nc, const int32_t *__restrict__ start, const int32_t *__re
         // the coarse level's first Jacobi sweep from zero, e_c = omega r_c / D_c
         if (ec_first) ec_first[a] = omega * s / Dc[a];
     }
+}
+
+// ---------------------------------------------------------------- restriction operator
+// The down leg of a cycle whose pre-smoothing is one Jacobi sweep from zero,
+// e = omega D^-1 r, followed by the residual and its restriction (the
+// agglomeration's summation, Sec. 4.3):
+//   r_c = P^T (r - A e) = P^T (I - omega A D^-1) r = R r,
+//   R_cj = sum over the members i of c, ascending, of (1 - omega) when
+//          j = i and -omega a_ij / D_j for the entries a_ij of row i.
+// One pass over R replaces the residual kernel (which writes t) and the
+// restriction (which reads it back through the member lists); the two are
+// equal up to rounding.  valT holds R for A^T (a_ji).
+
+// entries a coarse row gathers before merging: its members' row entries and
+// their diagonals
+__global__ void k_rop_count(int32_t nc, const int32_t *__restrict__ start,
+                            const int32_t *__restrict__ cells, Sell A, int64_t *cnt) {
+    GRID_STRIDE(c, nc) {
+        int64_t m = 0;
+        for (int32_t k = start[c]; k < start[c + 1]; ++k) {
+            const int32_t i = cells[k];
+            const int64_t ps = A.iperm ? (int64_t)A.iperm[i] : (int64_t)i;
+            const int w = row_len(A, ps);
+            m += 1;
+            for (int q = 0; q < w; ++q) m += A.col[entry_at(A, ps, q)] != i;  // padding: col i
+        }
+        cnt[c] = m;
+    }
+}
+
+// per coarse row: the member contributions in member order, each member's in
+// column order, as (column, source) pairs (source: the entry's position in
+// the level's slices, or -1 for a member's own diagonal); a stable insertion
+// sort by column keeps equal columns in member order.  rdeg: the number of
+// distinct columns.
+__global__ void k_rop_gather(int32_t nc, const int32_t *__restrict__ start,
+                             const int32_t *__restrict__ cells, Sell A,
+                             const int64_t *__restrict__ tstart, int32_t *tcol, int64_t *tsrc,
+                             int32_t *rdeg) {
+    GRID_STRIDE(c, nc) {
+        const int64_t o = tstart[c];
+        int m = 0;
+        auto push = [&](int32_t j, int64_t src) {
+            tcol[o + m] = j;
+            tsrc[o + m] = src;
+            ++m;
+        };
+        for (int32_t k = start[c]; k < start[c + 1]; ++k) {
+            const int32_t i = cells[k];
+            const int64_t ps = A.iperm ? (int64_t)A.iperm[i] : (int64_t)i;
+            const int w = row_len(A, ps);
+            bool diag = false;
+            for (int q = 0; q < w; ++q) {
+                const int64_t e = entry_at(A, ps, q);
+                const int32_t j = A.col[e];
+                if (j == i) continue;
+                if (!diag && j > i) {
+                    push(i, -1);
+                    diag = true;
+                }
+                push(j, e);
+            }
+            if (!diag) push(i, -1);
+        }
+        int u = 0;
+        for (int a = 0; a < m; ++a) {
+            const int32_t kc = tcol[o + a];
+            const int64_t ks = tsrc[o + a];
+            int b = a - 1;
+            while (b >= 0 && tcol[o + b] > kc) {
+                tcol[o + b + 1] = tcol[o + b];
+                tsrc[o + b + 1] = tsrc[o + b];
+                --b;
+            }
+            tcol[o + b + 1] = kc;
+            tsrc[o + b + 1] = ks;
+        }
+        for (int a = 0; a < m; ++a) u += a == 0 || tcol[o + a] != tcol[o + a - 1];
+        rdeg[c] = u;
+    }
+}
+
+// R's columns, and for each entry of R the run of its sources in the sorted
+// pairs (start, count)
+__global__ void k_rop_link(int32_t nc, Sell R, const int64_t *__restrict__ tstart,
+                           const int32_t *__restrict__ tcol, int64_t *rs0, int32_t *rsn) {
+    GRID_STRIDE(c, nc) {
+        const int64_t ps = R.iperm[c], o = tstart[c], o1 = tstart[c + 1];
+        int q = 0;
+        for (int64_t a = o; a < o1;) {
+            int64_t b = a + 1;
+            while (b < o1 && tcol[b] == tcol[a]) ++b;
+            const int64_t e = entry_at(R, ps, q++);
+            R.col[e] = tcol[a];
+            rs0[e] = a;
+            rsn[e] = (int32_t)(b - a);
+            a = b;
+        }
+    }
+}
+
+// values of R (and of its A^T form) from the level's coefficients: each entry
+// sums its sources in member order, (1 - omega) for a diagonal and
+// -omega a / D_j for an entry a of column j
+__global__ void k_rop_values(int64_t nnz, Sell R, const int64_t *__restrict__ rs0,
+                             const int32_t *__restrict__ rsn, const int64_t *__restrict__ src,
+                             const double *__restrict__ aval, const double *__restrict__ avalT,
+                             const double *__restrict__ D, double omega) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const double dj = D[R.col[e]];
+        double v = 0.0, vT = 0.0;
+        for (int64_t k = rs0[e]; k < rs0[e] + rsn[e]; ++k) {
+            const int64_t q = src[k];
+            if (q < 0) {
+                v = v + (1.0 - omega);
+                vT = vT + (1.0 - omega);
+            } else {
+                v = v + (-omega * aval[q]) / dj;
+                vT = vT + (-omega * avalT[q]) / dj;
+            }
+        }
+        R.val[e] = v;
+        R.valT[e] = vT;
+    }
+}
+
+__global__ void k_rop_f32(const double *a, float *b, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+// cycles whose down leg R replaces: Jacobi, one pre-sweep, no correction
+// scaling (which needs the residual itself)
+static bool rop_cycle(const ldu_gamg_opts &o) {
+    return o.smoother == LDU_SMOOTH_JACOBI && o.n_pre == 1 && !o.scale_correction;
+}
+
+// r_c = R r (row c: columns ascending, from zero), and the coarse level's
+// first Jacobi sweep from zero e_c = omega r_c / D_c when ec_first is given
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_rrestrict(SellView<T> R, const T *__restrict__ r, T *__restrict__ rc,
+               T *__restrict__ ec_first, const T *__restrict__ Dc, T omega,
+               const DevScalars *ds) {
+    if (vc_skip(ds)) return;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(R.nslices, [&](int64_t s) {
+        const int64_t p = s * kWave + lane;
+        if (p < R.n) {
+            const int32_t c = R.perm[p];
+            T acc = T(0);
+            row_entries<true, kCmpBatch>(R, s, lane, Direct<T>{r},
+                                         [&](int32_t, T v, T xv) { acc = acc + v * xv; });
+            rc[c] = acc;
+            if (ec_first) ec_first[c] = omega * acc / Dc[c];
+        }
+    });
 }
 
 // c = P e_c; s = (c . t) / (c . A c), or 1 when c.Ac is ~0
@@ -1215,6 +1385,13 @@ template <>
 SellView<float> lview<float>(const Level &L, bool tr) { return L.A.view32(tr); }
 
 template <typename T>
+static SellView<T> rview(const Level &L, bool tr);
+template <>
+SellView<double> rview<double>(const Level &L, bool tr) { return L.R.view(tr); }
+template <>
+SellView<float> rview<float>(const Level &L, bool tr) { return L.R.view32(tr); }
+
+template <typename T>
 static T *lvec(Level &L, int which);
 template <>
 double *lvec<double>(Level &L, int which) {
@@ -1287,15 +1464,23 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
             std::swap(e, e2);
         }
     }
-    if (A.pdeg) k_vc_resid<true, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
-    else k_vc_resid<false, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
     Level &C = h->levels[l + 1];
     T *rc = lvec<T>(C, 0);
     // the coarse level's first Jacobi sweep rides on the restriction
     const bool c_first = !gs && c.o->n_pre > 0 && l + 2 < h->levels.size();
-    k_vc_restrict<T><<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, t, rc,
-                                                    c_first ? lvec<T>(C, 1) : nullptr,
-                                                    lview<T>(C, c.tr).diag, omega, h->dev);
+    T *ec_first = c_first ? lvec<T>(C, 1) : nullptr;
+    const SellView<T> R = rview<T>(L, c.tr);
+    if (rop_cycle(*c.o) && L.r_ready && L.r_omega == c.o->omega && R.val) {
+        // residual and restriction in one pass over R (t is not formed)
+        k_vc_rrestrict<T><<<stream_grid_slices(R.nslices), kBlock, 0, st>>>(
+            R, r, rc, ec_first, lview<T>(C, c.tr).diag, omega, h->dev);
+    } else {
+        if (A.pdeg) k_vc_resid<true, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
+        else k_vc_resid<false, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
+        k_vc_restrict<T><<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, t, rc,
+                                                        ec_first, lview<T>(C, c.tr).diag, omega,
+                                                        h->dev);
+    }
     // without correction scaling, on levels small enough to be bound by launch
     // latency, the coarse level applies e += P e_c itself (a scatter through
     // the member lists: on large levels the gather form of k_vc_correct moves
@@ -1343,7 +1528,64 @@ static void ensure_work32(ldu_t *h, hipStream_t st) {
 // buffers and factors a cycle needs beyond the hierarchy: the second
 // ping-pong vector of the two-stage smoother (three or more inner steps) and
 // the DIC pivots of the coarsest level
+// R's structure for level l (once per hierarchy): its slices and, per
+// entry, the run of sources its value sums
+static void rop_structure(ldu_t *h, size_t l, hipStream_t st) {
+    Level &L = h->levels[l];
+    const Level &C = h->levels[l + 1];
+    Arena tmp;
+    int64_t *cnt = tmp.get<int64_t>(C.n);
+    int64_t *tstart = tmp.get<int64_t>(C.n + 1);
+    k_rop_count<<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, L.A, cnt);
+    exclusive_scan_i64(cnt, tstart, C.n, tmp, st);
+    int64_t total = 0;
+    HIP_CHECK(hipMemcpyAsync(&total, tstart + C.n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    int32_t *tcol = tmp.get<int32_t>(total);
+    L.r_src = h->gamg_arena.get<int64_t>(total);
+    int32_t *rdeg = tmp.get<int32_t>(C.n);
+    k_rop_gather<<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, L.A, tstart, tcol,
+                                                L.r_src, rdeg);
+    build_sliced_rows(L.R, C.n, rdeg, h->gamg_arena, st);
+    L.r_src0 = h->gamg_arena.get<int64_t>(L.R.nnz);
+    L.r_srcn = h->gamg_arena.get<int32_t>(L.R.nnz);
+    k_rop_link<<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.R, tstart, tcol, L.r_src0, L.r_srcn);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));  // tmp is released after this point
+    L.r_ready = false;
+}
+
+// R for every level but the coarsest, for the cycles whose down leg it
+// replaces: structure once per hierarchy, values again after new
+// coefficients or another omega, FP32 copies once the FP32 path is in use
+static void ensure_rop(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
+    if (!rop_cycle(o)) return;
+    const bool f32 = h->L0.A.val32 != nullptr;
+    for (size_t l = 0; l + 1 < h->levels.size(); ++l) {
+        Level &L = h->levels[l];
+        Sell &R = L.R;
+        if (!R.sptr) rop_structure(h, l, st);
+        const bool fresh = L.r_ready && L.r_omega == o.omega;
+        if (!fresh) {
+            k_rop_values<<<grid_n(R.nnz), kBlock, 0, st>>>(R.nnz, R, L.r_src0, L.r_srcn, L.r_src,
+                                                          L.A.val, L.A.valT, L.A.diag, o.omega);
+            L.r_omega = o.omega;
+            L.r_ready = true;
+        }
+        if (f32 && (!fresh || !R.val32)) {
+            if (!R.val32) {
+                R.val32 = h->gamg_arena.get<float>(R.nnz);
+                R.valT32 = h->gamg_arena.get<float>(R.nnz);
+            }
+            k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.val, R.val32, R.nnz);
+            k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.valT, R.valT32, R.nnz);
+        }
+        HIP_CHECK(hipGetLastError());
+    }
+}
+
 static VCtx make_ctx(ldu_t *h, const ldu_gamg_opts &o, bool tr, hipStream_t st) {
+    ensure_rop(h, o, st);
     if (o.smoother == LDU_SMOOTH_GS2 && o.gs_inner >= 3) {
         for (auto &L : h->levels) {
             if (!L.w) L.w = h->gamg_arena.get<double>(L.n);

@@ -169,6 +169,15 @@ struct Level {
     // else ~f), and per coarse cell its internal fine faces (ciStart, ciFace)
     int64_t *cfStart = nullptr, *ciStart = nullptr;
     int32_t *cfFace = nullptr, *ciFace = nullptr;
+    // the down leg of a cycle with one Jacobi pre-sweep from zero as one
+    // operator: R = P^T (I - omega A D^-1), a row per coarse cell over this
+    // level's columns, in compressed slices (valT: the same for A^T)
+    Sell R;
+    int64_t *r_src = nullptr;             // sources of R's entries, by entry in runs:
+    int64_t *r_src0 = nullptr;            //   first source of each entry of R
+    int32_t *r_srcn = nullptr;            //   and their count (source -1: a diagonal)
+    double r_omega = 0.0;                 // omega the values of R were made for
+    bool r_ready = false;                 // R's values match the coefficients
     int singular = 0;                     // coarsest level: A 1 = 0
     int max_row = 0;                      // longest row (off-diagonal entries)
     // V-cycle work vectors
@@ -225,6 +234,8 @@ inline int64_t slices_of(int64_t n) { return (n + kWave - 1) / kWave; }
 // relayout.hip
 void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t st);
 void set_level_values(Level &L, hipStream_t st);   // face values -> SELL values
+void build_sliced_rows(Sell &A, int32_t n, const int32_t *deg, Arena &ar,
+                       hipStream_t st);  // compressed slices for given row lengths
 void assemble_pressure(ldu_t *h, const double *gamma, const double *w, const double *mag_sf,
                        const double *delta, const double *diag_bc, const double *phi,
                        const double *b_bc, double *b, hipStream_t st);

@@ -525,6 +525,41 @@ void build_level_sell(ldu_t *h, Arena &ar, Level &L, bool validate, hipStream_t 
     HIP_CHECK(hipStreamSynchronize(st));  // tmp is released after this point
 }
 
+// compressed slices for n rows of the given lengths (device array): the
+// lane order, slice starts and offset tables, and uninitialised col, val and
+// valT arrays of the total entry count (no diagonal)
+void build_sliced_rows(Sell &A, int32_t n, const int32_t *deg, Arena &ar, hipStream_t st) {
+    Arena tmp;
+    const int64_t S = slices_of(n);
+    A = Sell{};
+    A.n = n;
+    A.nslices = S;
+    A.perm = ar.get<int32_t>(S * kWave);
+    A.iperm = ar.get<int32_t>(n);
+    A.pdeg = ar.get<int32_t>(S * kWave);
+    k_slice_sort<<<grid_for(S * kWave), kBlock, 0, st>>>(n, S, deg, A.perm, A.iperm, A.pdeg);
+    int64_t *entries = tmp.get<int64_t>(S);
+    int32_t *tlen = tmp.get<int32_t>(S);
+    k_slice_sizes<<<grid_for(S), kBlock, 0, st>>>(S, A.pdeg, entries, tlen);
+    A.sptr = ar.get<int64_t>(S + 1);
+    exclusive_scan_i64(entries, A.sptr, S, tmp, st);
+    A.tptr = ar.get<int32_t>(S + 1);
+    scan_counts_i32(tlen, A.tptr, S, tmp, st);
+    int32_t ntab = 0;
+    int64_t nnz = 0;
+    HIP_CHECK(hipMemcpyAsync(&ntab, A.tptr + S, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(&nnz, A.sptr + S, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    A.otab = ar.get<int32_t>(ntab);
+    k_slice_table<<<grid_for(S), kBlock, 0, st>>>(S, A.pdeg, A.tptr, A.otab);
+    A.nnz = nnz;
+    A.col = ar.get<int32_t>(nnz);
+    A.val = ar.get<double>(nnz);
+    A.valT = ar.get<double>(nnz);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));  // tmp is released after this point
+}
+
 void set_level_values(Level &L, hipStream_t st) {
     if (L.nf > 0)
         k_set_values<<<grid_for(L.nf), kBlock, 0, st>>>(L.nf, L.slotU, L.slotL, L.upper,

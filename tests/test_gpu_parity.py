@@ -388,6 +388,61 @@ def test_pcg_gamg_matches_oracle(name):
     assert true_res(c, x.cpu().numpy()) <= 1e-8
 
 
+ONE_SWEEP = dict(n_pre=1, n_post=1, scale_correction=0)
+
+
+@pytest.mark.parametrize("name", ["ragged", "c5s", "nonsym", "c3s"])
+def test_one_sweep_cycles_fuse_the_down_leg(name):
+    """One Jacobi pre-sweep from zero and no correction scaling: each level's
+    residual and restriction run as one product with R = P^T (I - w A D^-1).
+    Against the oracle's two-step cycle: single V-cycles at two values of w
+    (the second rebuilds R), CG + V-cycle forward, transposed and in mixed
+    precision, standalone GAMG, and a V-cycle after new coefficients (R's
+    values refreshed)."""
+    from meshgen import assemble_diag
+    c = _gamg_case(name)
+    A = O.Ldu.from_case(c)
+    m = _lib().from_case(c)
+    g = O.Gamg(A)
+    r = np.random.default_rng(41).standard_normal(c.n_cells)
+    if c.singular:
+        r -= r.mean()
+    for omega in (0.75, 0.6, 0.75):
+        e = m.vcycle(_t(r), omega=omega, **ONE_SWEEP).cpu().numpy()
+        ref = g.vcycle(r, n_pre=1, n_post=1, omega=omega, scale=False)
+        assert np.linalg.norm(e - ref) <= 1e-11 * np.linalg.norm(ref), omega
+    b = c.rhs[0]
+    m.gamg_setup(**ONE_SWEEP)  # a fresh hierarchy: R built again
+    x, st = m.pcg(_t(b), precond=2, rel_tol=1e-8, history=500)
+    ref = g.pcg(b, tol=1e-8, n_pre=1, n_post=1)
+    assert st.converged and st.iterations == ref.iterations
+    assert hist_close(st.history, ref.history, 1e-8)
+    xg, xr = x.cpu().numpy(), ref.x
+    if c.singular:
+        xg, xr = xg - xg.mean(), xr - xr.mean()
+    assert np.linalg.norm(xg - xr) <= 1e-9 * np.linalg.norm(xr)
+    xt, stt = m.adjoint(_t(b), solver="pcg", precond=2, rel_tol=1e-8)
+    reft = g.pcg(b, tol=1e-8, n_pre=1, n_post=1, transpose=True)
+    assert stt.converged and stt.iterations == reft.iterations
+    assert np.linalg.norm(b - O.tmul(A, xt.cpu().numpy())) <= 1e-8 * np.linalg.norm(b)
+    xm, sm = m.pcg(_t(b), precond=2, rel_tol=1e-12, precision="mixed")
+    assert sm.converged and true_res(c, xm.cpu().numpy()) <= 1e-12
+    if name in ("ragged", "nonsym"):  # standalone GAMG converges here without scaling
+        xs, ss = m.gamg(_t(b), rel_tol=1e-8, history=300, **ONE_SWEEP)
+        refs = g.solve(b, tol=1e-8, n_pre=1, n_post=1, scale=False)
+        assert ss.converged and ss.iterations == refs.iterations
+        assert hist_close(ss.history, refs.history)
+    if name == "c5s":  # new coefficients on the same aggregation
+        a2 = c.upper * np.exp(0.3 * np.random.default_rng(42).standard_normal(c.n_faces))
+        d2 = assemble_diag(c.n_cells, c.owner, c.neighbour, a2, a2, c.meta["a_boundary"])
+        m.set_coeffs(_t(d2), _t(a2), _t(a2))
+        g.set_values(d2, a2, a2)
+        e = m.vcycle(_t(r), **ONE_SWEEP).cpu().numpy()
+        ref = g.vcycle(r, n_pre=1, n_post=1, scale=False)
+        assert np.linalg.norm(e - ref) <= 1e-11 * np.linalg.norm(ref)
+    m.close()
+
+
 def test_set_coeffs_recomputes_cached_hierarchy():
     from meshgen import assemble_diag
     c = _gamg_case("c5s")

@@ -957,17 +957,22 @@ struct EpiScale {
     }
 };
 
-// e += s c
+// e += s c.  With rfirst, e is the first Jacobi sweep from zero, formed here
+// as omega r / D (the same expression as k_vc_first) instead of being read.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_vc_correct(int32_t n, int64_t S, const T *__restrict__ ec, const int32_t *__restrict__ agg,
-             T *__restrict__ e, int use_s, const DevScalars *ds) {
+             T *__restrict__ e, int use_s, const T *__restrict__ rfirst,
+             const T *__restrict__ D, T omega, const DevScalars *ds) {
     if (vc_skip(ds)) return;
     const T sc = use_s ? (T)ds->s : T(1);
     const int lane = threadIdx.x & 63;
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
-        if (i < n) e[i] = e[i] + sc * ec[agg[i]];
+        if (i < n) {
+            const T e0 = rfirst ? omega * rfirst[i] / D[i] : e[i];
+            e[i] = e0 + sc * ec[agg[i]];
+        }
     });
 }
 
@@ -1451,13 +1456,23 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
     const T omega = (T)c.o->omega;
     const bool gs = c.o->smoother == LDU_SMOOTH_GS2;
     T *w1 = lvec<T>(L, 4);
+    const SellView<T> R = rview<T>(L, c.tr);
+    const bool rop = rop_cycle(*c.o) && L.r_ready && L.r_omega == c.o->omega && R.val;
+    // without correction scaling, on levels small enough to be bound by launch
+    // latency, the coarse level applies e += P e_c itself (a scatter through
+    // the member lists: on large levels the gather form of k_vc_correct moves
+    // fewer bytes)
+    const bool fuse_corr = !c.o->scale_correction && L.n <= kFuseCorrRows;
+    // with the one-pass down leg nothing reads the first sweep before the
+    // correction, which then forms it itself
+    const bool defer_first = rop && !e_ready && !fuse_corr;
     if (gs) {  // forward two-stage Gauss-Seidel sweeps, the first from e = 0
         if (c.o->n_pre == 0) k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
         for (int k = 0; k < c.o->n_pre; ++k)
             gs_sweep<T>(A, r, e, t, e2, w1, k == 0, false, c.o->gs_inner, h->dev, G, st);
     } else {
         if (c.o->n_pre == 0) k_vc_zero<T><<<G, kBlock, 0, st>>>(L.n, S, e, h->dev);
-        else if (!e_ready)
+        else if (!e_ready && !defer_first)
             k_vc_first<T><<<G, kBlock, 0, st>>>(L.n, S, r, A.diag, e, omega, h->dev);
         for (int k = 1; k < c.o->n_pre; ++k) {
             launch_jacobi<T>(A, r, e, e2, omega, nullptr, nullptr, {}, h->dev, G, st);
@@ -1469,8 +1484,7 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
     // the coarse level's first Jacobi sweep rides on the restriction
     const bool c_first = !gs && c.o->n_pre > 0 && l + 2 < h->levels.size();
     T *ec_first = c_first ? lvec<T>(C, 1) : nullptr;
-    const SellView<T> R = rview<T>(L, c.tr);
-    if (rop_cycle(*c.o) && L.r_ready && L.r_omega == c.o->omega && R.val) {
+    if (rop) {
         // residual and restriction in one pass over R (t is not formed)
         k_vc_rrestrict<T><<<stream_grid_slices(R.nslices), kBlock, 0, st>>>(
             R, r, rc, ec_first, lview<T>(C, c.tr).diag, omega, h->dev);
@@ -1481,11 +1495,6 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
                                                         ec_first, lview<T>(C, c.tr).diag, omega,
                                                         h->dev);
     }
-    // without correction scaling, on levels small enough to be bound by launch
-    // latency, the coarse level applies e += P e_c itself (a scatter through
-    // the member lists: on large levels the gather form of k_vc_correct moves
-    // fewer bytes)
-    const bool fuse_corr = !c.o->scale_correction && L.n <= kFuseCorrRows;
     bool done_corr = false;
     const T *ec = vcycle<T>(c, l + 1, rc, nullptr, nullptr, c_first,
                             fuse_corr ? FineCorr<T>{e, L.aggStart, L.aggCells} : FineCorr<T>{},
@@ -1496,7 +1505,8 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
         launch_finalize<2>(h->partials, G, h->dev, EpiScale{}, st);
     }
     if (!done_corr)
-        k_vc_correct<T><<<G, kBlock, 0, st>>>(L.n, S, ec, L.agg, e, c.o->scale_correction, h->dev);
+        k_vc_correct<T><<<G, kBlock, 0, st>>>(L.n, S, ec, L.agg, e, c.o->scale_correction,
+                                             defer_first ? r : nullptr, A.diag, omega, h->dev);
     for (int k = 0; k < c.o->n_post; ++k) {
         const bool last = k + 1 == c.o->n_post;
         if (gs) {  // backward sweeps: the V-cycle stays symmetric

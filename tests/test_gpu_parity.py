@@ -443,6 +443,28 @@ def test_one_sweep_cycles_fuse_the_down_leg(name):
     m.close()
 
 
+def test_one_sweep_cycle_on_a_level_above_the_fused_correction_size():
+    """56^3 = 175,616 cells, above the size where the coarse level applies the
+    correction itself: level 0's first sweep is then formed by the correction
+    kernel.  CG + V-cycle against the oracle, forward and transposed."""
+    c = box_case(56, 56, 56, coeff="lognormal", nonsym=0.2, dirichlet_x0=1.0, seed=43)
+    A = O.Ldu.from_case(c)
+    g = O.Gamg(A)
+    m = _lib().from_case(c)
+    m.gamg_setup(**ONE_SWEEP)
+    b = c.rhs[0]
+    x, st = m.pcg(_t(b), precond=2, rel_tol=1e-8, history=500)
+    ref = g.pcg(b, tol=1e-8, n_pre=1, n_post=1)
+    assert st.converged and st.iterations == ref.iterations
+    assert hist_close(st.history, ref.history, 1e-8)
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    xt, stt = m.adjoint(_t(b), solver="pcg", precond=2, rel_tol=1e-8)
+    reft = g.pcg(b, tol=1e-8, n_pre=1, n_post=1, transpose=True)
+    assert stt.converged and stt.iterations == reft.iterations
+    assert np.linalg.norm(b - O.tmul(A, xt.cpu().numpy())) <= 1e-8 * np.linalg.norm(b)
+    m.close()
+
+
 def test_set_coeffs_recomputes_cached_hierarchy():
     from meshgen import assemble_diag
     c = _gamg_case("c5s")

@@ -539,6 +539,7 @@ static void galerkin(ldu_t *h, Level &F, Level &C, Arena &ar, hipStream_t st) {
 }
 
 static void ensure_rop(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st);
+static void refresh_rop(ldu_t *h, hipStream_t st);
 
 void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
     h->gamg_ready = false;
@@ -601,7 +602,7 @@ void gamg_refresh_values(ldu_t *h, hipStream_t st) {
     }
     detect_singular(h, h->levels.back(), st);
     h->dic_ready = false;
-    for (auto &L : h->levels) L.r_ready = false;
+    refresh_rop(h, st);
 }
 
 // DIC pivots of the coarsest level (diagonal incomplete Cholesky; the paper's
@@ -1565,6 +1566,20 @@ static void rop_structure(ldu_t *h, size_t l, hipStream_t st) {
     L.r_ready = false;
 }
 
+// R's values (and their FP32 copies, when present) for the given omega
+static void rop_values(Level &L, double omega, hipStream_t st) {
+    Sell &R = L.R;
+    k_rop_values<<<grid_n(R.nnz), kBlock, 0, st>>>(R.nnz, R, L.r_src0, L.r_srcn, L.r_src, L.A.val,
+                                                  L.A.valT, L.A.diag, omega);
+    if (R.val32) {
+        k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.val, R.val32, R.nnz);
+        k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.valT, R.valT32, R.nnz);
+    }
+    HIP_CHECK(hipGetLastError());
+    L.r_omega = omega;
+    L.r_ready = true;
+}
+
 // R for every level but the coarsest, for the cycles whose down leg it
 // replaces: structure once per hierarchy, values again after new
 // coefficients or another omega, FP32 copies once the FP32 path is in use
@@ -1576,22 +1591,20 @@ static void ensure_rop(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
         Sell &R = L.R;
         if (!R.sptr) rop_structure(h, l, st);
         const bool fresh = L.r_ready && L.r_omega == o.omega;
-        if (!fresh) {
-            k_rop_values<<<grid_n(R.nnz), kBlock, 0, st>>>(R.nnz, R, L.r_src0, L.r_srcn, L.r_src,
-                                                          L.A.val, L.A.valT, L.A.diag, o.omega);
-            L.r_omega = o.omega;
-            L.r_ready = true;
-        }
-        if (f32 && (!fresh || !R.val32)) {
-            if (!R.val32) {
-                R.val32 = h->gamg_arena.get<float>(R.nnz);
-                R.valT32 = h->gamg_arena.get<float>(R.nnz);
-            }
-            k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.val, R.val32, R.nnz);
-            k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.valT, R.valT32, R.nnz);
+        if (!fresh) rop_values(L, o.omega, st);
+        if (f32 && !R.val32) {
+            R.val32 = h->gamg_arena.get<float>(R.nnz);
+            R.valT32 = h->gamg_arena.get<float>(R.nnz);
+            rop_values(L, L.r_omega, st);
         }
         HIP_CHECK(hipGetLastError());
     }
+}
+
+// new level coefficients: R's values follow at once (same omega)
+static void refresh_rop(ldu_t *h, hipStream_t st) {
+    for (size_t l = 0; l + 1 < h->levels.size(); ++l)
+        if (h->levels[l].R.sptr && h->levels[l].r_ready) rop_values(h->levels[l], h->levels[l].r_omega, st);
 }
 
 static VCtx make_ctx(ldu_t *h, const ldu_gamg_opts &o, bool tr, hipStream_t st) {

@@ -220,10 +220,11 @@ int gamg_level_export(ldu_handle h, int level, int32_t *agg, int32_t *owner,
 /* Storage of level l's matrix in the product kernels (level 0 needs no GAMG
  * hierarchy; HOST outputs, either may be NULL).  compressed: 1 when the rows
  * sit in length-sorted compressed slices, 0 in plain slices of 64 rows.
- * col16: 1 when the kernels read each column as a 16-bit offset from the
- * smallest column of its slot (possible when every slot, the k-th entries of
- * a slice's rows, spans at most 65535 columns), 0 when they read 32-bit
- * columns.  Either way the products are the same bit for bit. */
+ * col16: 1 when the kernels read columns as 16-bit offsets from the
+ * smallest column of their slot (the k-th entries of a slice's rows) for the
+ * slots that span at most 65535 columns, the others reading 32-bit columns;
+ * 0 when every slot reads 32-bit columns.  Either way the products are the
+ * same bit for bit. */
 int ldu_level_layout(ldu_handle h, int level, int *compressed, int *col16);
 
 /* Adjoint solve A^T lambda = g on the transposed coefficients (upper and

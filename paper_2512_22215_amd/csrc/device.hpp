@@ -213,16 +213,22 @@ struct PlainWalk {
     // loads of a whole batch are in flight before the first wait on them.
     // The base is a scalar load per slot: those of one slice share a scalar
     // cache line.  (Reading a fixed batch of bases per step instead measured
-    // slower, with more HBM traffic.)
+    // slower, with more HBM traffic.)  A slot too wide for 16-bit offsets has
+    // base -1 and reads the 32-bit columns (a wave-uniform branch).
     __device__ __forceinline__ void load(int k, int32_t &raw, int32_t &base, T &v) const {
         const int64_t o = (int64_t)k * kWave;
-        base = C16 ? bp[k] : 0;
-        if constexpr (C16) raw = (int32_t)__builtin_nontemporal_load(hp + o);
-        else raw = __builtin_nontemporal_load(cp + o);
+        if constexpr (C16) {
+            base = bp[k];
+            if (base >= 0) raw = (int32_t)__builtin_nontemporal_load(hp + o);
+            else raw = __builtin_nontemporal_load(cp + o);
+        } else {
+            base = 0;
+            raw = __builtin_nontemporal_load(cp + o);
+        }
         v = __builtin_nontemporal_load(vp + o);
     }
     static __device__ __forceinline__ int32_t column(int32_t raw, int32_t base) {
-        return C16 ? base + raw : raw;
+        return C16 && base >= 0 ? base + raw : raw;
     }
 };
 

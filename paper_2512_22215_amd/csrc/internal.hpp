@@ -21,12 +21,13 @@
 //    own cache lines.
 //  - 16-bit columns: for each stored column k of a slice (a "slot": the k-th
 //    entries of the slice's rows), cbase holds the smallest column of the
-//    slot and c16 each entry's column minus that base.  Levels whose slots
-//    all span at most 65535 columns use them in the product kernels (2 bytes
-//    per entry instead of 4, and a shorter stream between the reuses of x);
-//    the others keep c16 = NULL and read the 32-bit columns.  The slot of
-//    (s, k) is (sptr[s] / 64) + k in plain slices and tptr[s] + k in
-//    compressed ones.
+//    slot and c16 each entry's column minus that base.  Slots that span at
+//    most 65535 columns use them in the product kernels (2 bytes per entry
+//    instead of 4, and a shorter stream between the reuses of x); wider
+//    slots have base -1 and read the 32-bit columns.  A level without any
+//    narrow slot keeps c16 = NULL.  The slot of (s, k) is (sptr[s] / 64) + k
+//    in plain slices and tptr[s] + k in compressed ones (which keep 32-bit
+//    columns).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -90,7 +91,7 @@ struct SellView {
     const int32_t *tptr;   // compressed slices: start of slice s in otab
     const int32_t *otab;   // compressed slices: offset of entry k within slice s
     const uint16_t *c16;   // column minus its slot base (NULL: use col)
-    const int32_t *cbase;  // smallest column of each slot
+    const int32_t *cbase;  // smallest column of each slot (-1: slot uses col)
 };
 
 // scalars shared between the kernels of one solve; device resident

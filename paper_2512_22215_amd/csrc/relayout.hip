@@ -369,7 +369,7 @@ __device__ __forceinline__ void slot_span(const int64_t *sptr, const int32_t *pd
 
 __global__ void k_col16_bases(int64_t S, const int64_t *sptr, const int32_t *pdeg,
                               const int32_t *tptr, const int32_t *otab, const int32_t *col,
-                              int32_t *cbase, int *wide) {
+                              int32_t *cbase, unsigned long long *narrow) {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S;
          s += (int64_t)gridDim.x * blockDim.x) {
         const int w = pdeg ? pdeg[s * kWave] : (int)((sptr[s + 1] - sptr[s]) >> 6);
@@ -383,8 +383,9 @@ __global__ void k_col16_bases(int64_t S, const int64_t *sptr, const int32_t *pde
                 lo = c < lo ? c : lo;
                 hi = c > hi ? c : hi;
             }
-            cbase[bi] = lo;
-            if ((int64_t)hi - lo > 65535) atomicOr(wide, 1);
+            const bool fits = (int64_t)hi - lo <= 65535;
+            cbase[bi] = fits ? lo : -1;  // -1: this slot reads the 32-bit columns
+            if (fits) atomicAdd(narrow, 1ull);
         }
     }
 }
@@ -399,12 +400,13 @@ __global__ void k_col16_fill(int64_t S, const int64_t *sptr, const int32_t *pdeg
             int64_t e0, bi;
             int cnt;
             slot_span(sptr, pdeg, tptr, otab, s, k, e0, cnt, bi);
-            for (int l = 0; l < cnt; ++l) c16[e0 + l] = (uint16_t)(col[e0 + l] - cbase[bi]);
+            const int32_t b = cbase[bi];
+            for (int l = 0; l < cnt; ++l) c16[e0 + l] = b >= 0 ? (uint16_t)(col[e0 + l] - b) : 0;
         }
     }
 }
 
-// 16-bit columns for a level whose slots are all narrow enough
+// 16-bit columns for the slots narrow enough, on a level that has any
 static void build_col16(Sell &A, int64_t nslots, Arena &ar, Arena &tmp, hipStream_t st) {
     A.c16 = nullptr;
     A.cbase = nullptr;
@@ -412,14 +414,14 @@ static void build_col16(Sell &A, int64_t nslots, Arena &ar, Arena &tmp, hipStrea
     // the narrower columns save (measured on the Galerkin levels)
     if (A.nnz == 0 || nslots == 0 || A.pdeg) return;
     int32_t *cbase = ar.get<int32_t>(nslots);
-    int *wide = tmp.get<int>(1);
-    k_fill_i32<<<1, kBlock, 0, st>>>(wide, 1, 0);
+    unsigned long long *narrow = tmp.get<unsigned long long>(1);
+    HIP_CHECK(hipMemsetAsync(narrow, 0, sizeof(unsigned long long), st));
     k_col16_bases<<<grid_for(A.nslices), kBlock, 0, st>>>(A.nslices, A.sptr, A.pdeg, A.tptr,
-                                                         A.otab, A.col, cbase, wide);
-    int hwide = 1;
-    HIP_CHECK(hipMemcpyAsync(&hwide, wide, sizeof(int), hipMemcpyDeviceToHost, st));
+                                                         A.otab, A.col, cbase, narrow);
+    unsigned long long hnarrow = 0;
+    HIP_CHECK(hipMemcpyAsync(&hnarrow, narrow, sizeof(hnarrow), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
-    if (hwide) return;
+    if (hnarrow == 0) return;
     uint16_t *c16 = ar.get<uint16_t>(A.nnz);
     k_col16_fill<<<grid_for(A.nslices), kBlock, 0, st>>>(A.nslices, A.sptr, A.pdeg, A.tptr,
                                                         A.otab, A.col, cbase, c16);

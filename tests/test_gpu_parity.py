@@ -75,19 +75,28 @@ def test_amul_tmul_bit_exact(name):
     assert np.array_equal(y32, O.amul_f32(A, x32))
 
 
-@pytest.mark.parametrize("order", ["natural", "random"])
-def test_column_storage_forms_bit_exact(order):
-    """A 48^3 box (110,592 cells, more than 16-bit columns can address):
-    numbered naturally, every slot of level 0 spans under 65536 columns and
-    the kernels read 16-bit column offsets; numbered at random, slots span
-    the whole range and they read 32-bit columns.  Both give the oracle's
-    Amul, Tmul and FP32 Amul bit for bit, and the same GAMG solve."""
-    c = box_case(48, 48, 48, coeff="lognormal", nonsym=0.3, dirichlet_x0=1.0, seed=31)
+@pytest.mark.parametrize("order,side", [("natural", 48), ("mixed", 48), ("random", 48),
+                                        ("random", 64)])
+def test_column_storage_forms_bit_exact(order, side):
+    """Boxes beyond what 16-bit columns can address (48^3 = 110,592 cells,
+    64^3 = 262,144).  A slot (the k-th entries of a slice's rows) that spans
+    at most 65535 columns is read as 16-bit offsets from its smallest column,
+    a wider one as 32-bit columns.  Natural numbering: every slot narrow.
+    The first 30% of the cells in order and the rest shuffled: both kinds in
+    one level (about 5% wide), as in random numbering at 48^3 (about 77%
+    wide).  Random numbering at 64^3: every slot wide, no 16-bit array.  All
+    give the oracle's Amul, Tmul and FP32 Amul bit for bit, and the same GAMG
+    solve."""
+    c = box_case(side, side, side, coeff="lognormal", nonsym=0.3, dirichlet_x0=1.0, seed=31)
     if order == "random":
         c = _perm(c, 32)
+    elif order == "mixed":
+        n0 = int(0.3 * c.n_cells)
+        tail = n0 + np.random.default_rng(34).permutation(c.n_cells - n0)
+        c = relabel(c, np.concatenate([np.arange(n0), tail]))
     m = _lib().from_case(c)
     lay = m.layout(0)
-    assert lay == {"compressed": False, "col16": order == "natural"}
+    assert lay == {"compressed": False, "col16": not (order == "random" and side == 64)}
     A = O.Ldu.from_case(c)
     x = np.random.default_rng(33).standard_normal(c.n_cells)
     assert np.array_equal(m.amul(_t(x)).cpu().numpy(), O.amul(A, x))

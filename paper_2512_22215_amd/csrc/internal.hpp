@@ -51,7 +51,7 @@ constexpr int kMaxGrid = 2048;     // streaming kernels: at most this many block
 // in L2 between its reuses one mesh plane apart.
 constexpr int kPlainF64ProductBlocks = 1024;
 #ifndef LDU_CMP_BATCH
-#define LDU_CMP_BATCH 16
+#define LDU_CMP_BATCH 24
 #endif
 constexpr int kCmpBatch = LDU_CMP_BATCH;  // compressed-slice row products: entries per batch
 constexpr int kMaxLevels = 64;

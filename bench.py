@@ -243,14 +243,20 @@ def main():
     b = torch.from_numpy(case.rhs[0]).to(dev)
     torch.cuda.synchronize()
 
+    # device memory the library holds (free HBM before and after; the inputs
+    # above are the caller's and already allocated)
+    free0 = torch.cuda.mem_get_info(dev)[0]
     t0 = time.perf_counter()
     m = LduMatrix(case.n_cells, own, nb, d, up, lo, device=dev)
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
+    free1 = torch.cuda.mem_get_info(dev)[0]
     t0 = time.perf_counter()
     m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    free2 = torch.cuda.mem_get_info(dev)[0]
+    mem = {"level0_bytes": free0 - free1, "hierarchy_bytes": free1 - free2}
     nlev = m.n_levels()
     log(f"[bench] ldu_create {t_create:.3f} s, gamg_setup {t_setup:.3f} s, {nlev} levels")
 
@@ -430,6 +436,7 @@ def main():
         "adjoint": adj_rec,
         "mixed_solve": mixed_rec,
         "setup_s": {"ldu_create": t_create, "gamg_setup": t_setup},
+        "device_memory": mem,
         "levels": nlev,
         "iterations": st.iterations,
         "true_residual": res,

@@ -120,7 +120,7 @@ def _timed(torch, fn, reps=2):
     return best, out
 
 
-def run_suite(torch, dev):
+def run_suite(torch, dev, only=None):
     """The runs each workload is defined for, timed on the GPU: c1 PCG; c2
     PCG, GAMG and CG + V-cycle in random and RCM numbering; c4 PCG FP64 and
     mixed over three warm-started right-hand sides, plus CG + V-cycle; c5
@@ -147,6 +147,9 @@ def run_suite(torch, dev):
 
     for name, kw in (("c1", {}), ("c2", {"order": "random"}), ("c2", {"order": "rcm"}),
                      ("c4", {}), ("c5", {})):
+        label = name + ("-rcm" if kw.get("order") == "rcm" else "")
+        if only and label != only:
+            continue
         t0 = time.perf_counter()
         case = config_case(name, **kw)
         log(f"[suite] {case.name}: {case.n_cells} cells ({time.perf_counter() - t0:.1f} s "
@@ -216,6 +219,8 @@ def main():
     ap.add_argument("--suite", action="store_true",
                     help="instead of the headline step, time the runs of every workload "
                          "(c1, c2 random and RCM, c4, c5), one JSON line each")
+    ap.add_argument("--only", default=None,
+                    help="with --suite: run one workload (c1, c2, c2-rcm, c4, c5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -229,7 +234,7 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.suite:
-        run_suite(torch, dev)
+        run_suite(torch, dev, args.only)
         return
     t0 = time.perf_counter()
     case = config_case("c3", n=args.n)

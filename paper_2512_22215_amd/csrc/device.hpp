@@ -256,13 +256,13 @@ __device__ __forceinline__ void plain_entries(const SellView<T> &A, int64_t s, i
     }
 }
 
+// the entries of a compressed-slice row whose slice starts at b0 and whose
+// length is w (see cmp_entries)
 template <int B, typename T, class XA, class F>
-__device__ __forceinline__ void cmp_entries(const SellView<T> &A, int64_t s, int lane,
-                                            const XA &xa, F &&f) {
-    const int64_t b0 = A.sptr[s];
+__device__ __forceinline__ void cmp_entries_at(const SellView<T> &A, int64_t b0, int w, int lane,
+                                               const XA &xa, F &&f) {
     const int32_t *cp = A.col + b0 + lane;
     const T *vp = A.val + b0 + lane;
-    const int w = A.pdeg[s * kWave + lane];
     SliceOffsets so;
     for (int k = 0; k < w; k += B) {
         int32_t c[B];
@@ -290,6 +290,63 @@ __device__ __forceinline__ void cmp_entries(const SellView<T> &A, int64_t s, int
 // B at a time: f(column, value, x[column]) for each, in column order.  Plain
 // slices walk their slots with PlainWalk; compressed slices loop per lane to
 // the row's own length, with ballot-counted offsets.
+template <int B, typename T, class XA, class F>
+__device__ __forceinline__ void cmp_entries(const SellView<T> &A, int64_t s, int lane,
+                                            const XA &xa, F &&f) {
+    cmp_entries_at<B>(A, A.sptr[s], A.pdeg[s * kWave + lane], lane, xa, f);
+}
+
+// The header of a compressed slice as one lane needs it: the slice start, and
+// the length and row index of the lane's row (0 and -1 past the level's last
+// row: pdeg and perm cover whole slices).
+struct CmpHead {
+    int64_t b0 = 0;
+    int w = 0;
+    int32_t row = -1;
+};
+
+template <typename T>
+__device__ __forceinline__ CmpHead cmp_head(const SellView<T> &A, int64_t s, int lane) {
+    CmpHead h;
+    const int64_t p = s * kWave + lane;
+    h.b0 = A.sptr[s];
+    h.w = A.pdeg[p];
+    h.row = A.perm[p];
+    return h;
+}
+
+// for_each_slice over compressed slices, software-pipelined: the header of a
+// wave's next slice is loaded before the current slice is processed, so its
+// round trip overlaps the current slice's entry loads and gathers.
+// f(s, head); lanes whose head.row is -1 hold no row.
+template <typename T, class F>
+__device__ __forceinline__ void for_each_cmp_slice(const SellView<T> &A, F &&f) {
+    const int64_t S = A.nslices;
+    const int lane = threadIdx.x & 63;
+    const int G = gridDim.x;
+    const int nx = (G >= 64 && (G & 7) == 0) ? 8 : 1;
+    const int64_t x = blockIdx.x % nx;
+    const int64_t j = blockIdx.x / nx;
+    const int64_t Gx = G / nx;
+    const int64_t R = (S + nx - 1) / nx;
+    const int64_t lo = x * R;
+    const int64_t hi = (lo + R < S) ? lo + R : S;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    CmpHead h;
+    {
+        const int64_t s0 = lo + j * kWavesPerBlock + w;
+        if (s0 < hi) h = cmp_head(A, s0, lane);
+    }
+    for (int64_t g = j; lo + g * kWavesPerBlock < hi; g += Gx) {
+        const int64_t s = lo + g * kWavesPerBlock + w;
+        const int64_t sn = s + Gx * kWavesPerBlock;
+        CmpHead hn;
+        if (sn < hi) hn = cmp_head(A, sn, lane);
+        if (s < hi) f(s, h);
+        h = hn;
+    }
+}
+
 template <bool CMP, int B, typename T, class XA, class F>
 __device__ __forceinline__ void row_entries(const SellView<T> &A, int64_t s, int lane,
                                             const XA &xa, F &&f) {

@@ -693,17 +693,31 @@ k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
     if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
-    for_each_slice<product_cap<CMP, T>()>(A.nslices, [&](int64_t s) {
-        const int64_t p = s * kWave + lane;
-        if (p < A.n) {
-            const int32_t i = sv_row<CMP>(A, p);
-            const T y = sell_row<CMP>(A, s, lane, i, Direct<T>{e});
-            const T zi = e[i] + omega * (r[i] - y) / A.diag[i];
-            eo[i] = zi;
-            if constexpr (DOT) acc[0] += (double)rdot[i] * (double)zi;
-            if constexpr (CORR) fc(i, zi);
-        }
-    });
+    auto finish = [&](int32_t i, T y) {
+        const T zi = e[i] + omega * (r[i] - y) / A.diag[i];
+        eo[i] = zi;
+        if constexpr (DOT) acc[0] += (double)rdot[i] * (double)zi;
+        if constexpr (CORR) fc(i, zi);
+    };
+    if constexpr (CMP) {
+        for_each_cmp_slice(A, [&](int64_t, const CmpHead &hd) {
+            if (hd.row >= 0) {
+                const int32_t i = hd.row;
+                T y = A.diag[i] * e[i];  // the row's order: diagonal, then columns
+                cmp_entries_at<kCmpBatch>(A, hd.b0, hd.w, lane, Direct<T>{e},
+                                          [&](int32_t, T v, T xv) { y = y + v * xv; });
+                finish(i, y);
+            }
+        });
+    } else {
+        for_each_slice<product_cap<CMP, T>()>(A.nslices, [&](int64_t s) {
+            const int64_t p = s * kWave + lane;
+            if (p < A.n) {
+                const int32_t i = (int32_t)p;
+                finish(i, sell_row<CMP>(A, s, lane, i, Direct<T>{e}));
+            }
+        });
+    }
     if constexpr (DOT) block_partials<1>(acc, partials);
 }
 
@@ -917,13 +931,12 @@ k_vc_rrestrict(SellView<T> R, const T *__restrict__ r, T *__restrict__ rc,
                const DevScalars *ds) {
     if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
-    for_each_slice(R.nslices, [&](int64_t s) {
-        const int64_t p = s * kWave + lane;
-        if (p < R.n) {
-            const int32_t c = R.perm[p];
+    for_each_cmp_slice(R, [&](int64_t, const CmpHead &hd) {
+        if (hd.row >= 0) {
+            const int32_t c = hd.row;
             T acc = T(0);
-            row_entries<true, kCmpBatch>(R, s, lane, Direct<T>{r},
-                                         [&](int32_t, T v, T xv) { acc = acc + v * xv; });
+            cmp_entries_at<kCmpBatch>(R, hd.b0, hd.w, lane, Direct<T>{r},
+                                      [&](int32_t, T v, T xv) { acc = acc + v * xv; });
             rc[c] = acc;
             if (ec_first) ec_first[c] = omega * acc / Dc[c];
         }

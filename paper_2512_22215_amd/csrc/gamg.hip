@@ -813,11 +813,54 @@ __global__ void k_rop_count(int32_t nc, const int32_t *__restrict__ start,
     }
 }
 
+// a member row's entries in column order, with the diagonal at its place:
+// (col, src) with src the entry's position in the level's slices, or -1 for
+// the diagonal; valid is false past the end
+struct RowCursor {
+    int32_t i = 0, col = 0;
+    int64_t ps = 0, src = 0;
+    int w = 0, q = 0;
+    bool diag = false, valid = false;
+    __device__ void init(const Sell &A, int32_t row) {
+        i = row;
+        ps = A.iperm ? (int64_t)A.iperm[row] : (int64_t)row;
+        w = row_len(A, ps);
+        q = 0;
+        diag = false;
+        next(A);
+    }
+    __device__ void next(const Sell &A) {
+        while (q < w) {
+            const int64_t e = entry_at(A, ps, q);
+            const int32_t j = A.col[e];
+            if (j == i) {  // padding points at the row
+                ++q;
+                continue;
+            }
+            if (!diag && j > i) break;
+            col = j;
+            src = e;
+            ++q;
+            valid = true;
+            return;
+        }
+        if (!diag) {
+            col = i;
+            src = -1;
+            diag = true;
+            valid = true;
+            return;
+        }
+        valid = false;
+    }
+};
+
 // per coarse row: the member contributions in member order, each member's in
 // column order, as (column, source) pairs (source: the entry's position in
-// the level's slices, or -1 for a member's own diagonal); a stable insertion
-// sort by column keeps equal columns in member order.  rdeg: the number of
-// distinct columns.
+// the level's slices, or -1 for a member's own diagonal), ordered by column
+// with equal columns in member order: a merge of the two rows of a pair, or a
+// stable insertion sort of the concatenated rows of a larger aggregate.
+// rdeg: the number of distinct columns.
 __global__ void k_rop_gather(int32_t nc, const int32_t *__restrict__ start,
                              const int32_t *__restrict__ cells, Sell A,
                              const int64_t *__restrict__ tstart, int32_t *tcol, int64_t *tsrc,
@@ -830,7 +873,26 @@ __global__ void k_rop_gather(int32_t nc, const int32_t *__restrict__ start,
             tsrc[o + m] = src;
             ++m;
         };
-        for (int32_t k = start[c]; k < start[c + 1]; ++k) {
+        const int32_t k0 = start[c], k1 = start[c + 1];
+        if (k1 - k0 <= 2) {
+            RowCursor a, b;
+            a.init(A, cells[k0]);
+            if (k1 - k0 == 2) b.init(A, cells[k0 + 1]);
+            while (a.valid || b.valid) {
+                if (a.valid && (!b.valid || a.col <= b.col)) {
+                    push(a.col, a.src);
+                    a.next(A);
+                } else {
+                    push(b.col, b.src);
+                    b.next(A);
+                }
+            }
+            int u = 0;
+            for (int t = 0; t < m; ++t) u += t == 0 || tcol[o + t] != tcol[o + t - 1];
+            rdeg[c] = u;
+            continue;
+        }
+        for (int32_t k = k0; k < k1; ++k) {
             const int32_t i = cells[k];
             const int64_t ps = A.iperm ? (int64_t)A.iperm[i] : (int64_t)i;
             const int w = row_len(A, ps);
@@ -1605,10 +1667,11 @@ static void ensure_rop(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
         if (!R.sptr) rop_structure(h, l, st);
         const bool fresh = L.r_ready && L.r_omega == o.omega;
         if (!fresh) rop_values(L, o.omega, st);
-        if (f32 && !R.val32) {
+        if (f32 && !R.val32) {  // values are current: only the FP32 copies are new
             R.val32 = h->gamg_arena.get<float>(R.nnz);
             R.valT32 = h->gamg_arena.get<float>(R.nnz);
-            rop_values(L, L.r_omega, st);
+            k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.val, R.val32, R.nnz);
+            k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.valT, R.valT32, R.nnz);
         }
         HIP_CHECK(hipGetLastError());
     }

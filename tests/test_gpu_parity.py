@@ -434,6 +434,10 @@ def test_one_sweep_cycles_fuse_the_down_leg(name):
     reft = g.pcg(b, tol=1e-8, n_pre=1, n_post=1, transpose=True)
     assert stt.converged and stt.iterations == reft.iterations
     assert np.linalg.norm(b - O.tmul(A, xt.cpu().numpy())) <= 1e-8 * np.linalg.norm(b)
+    # the transposed FP32 cycle (R's A^T values in FP32) inside FP64 refinement
+    xtm, stm = m.adjoint(_t(b), solver="pcg", precond=2, rel_tol=1e-12, precision="mixed")
+    assert stm.converged
+    assert np.linalg.norm(b - O.tmul(A, xtm.cpu().numpy())) <= 1e-12 * np.linalg.norm(b)
     xm, sm = m.pcg(_t(b), precond=2, rel_tol=1e-12, precision="mixed")
     assert sm.converged and true_res(c, xm.cpu().numpy()) <= 1e-12
     if name in ("ragged", "nonsym"):  # standalone GAMG converges here without scaling
@@ -471,6 +475,11 @@ def test_one_sweep_cycle_on_a_level_above_the_fused_correction_size():
     reft = g.pcg(b, tol=1e-8, n_pre=1, n_post=1, transpose=True)
     assert stt.converged and stt.iterations == reft.iterations
     assert np.linalg.norm(b - O.tmul(A, xt.cpu().numpy())) <= 1e-8 * np.linalg.norm(b)
+    for tr, solve in ((False, m.pcg), (True, lambda v, **kw: m.adjoint(v, solver="pcg", **kw))):
+        xm, sm = solve(_t(b), precond=2, rel_tol=1e-12, precision="mixed")
+        xm = xm.cpu().numpy()
+        res = b - (O.tmul(A, xm) if tr else O.amul(A, xm))
+        assert sm.converged and np.linalg.norm(res) <= 1e-12 * np.linalg.norm(b), tr
     m.close()
 
 

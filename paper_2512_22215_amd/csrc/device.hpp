@@ -20,6 +20,27 @@
 
 namespace ldu {
 
+// The slices a wave walks, for a grid of G blocks: with G a multiple of 8
+// (and at least 64) block b works in XCD b % 8's contiguous eighth of the
+// slices [lo, hi), starting at group j with stride Gx groups of
+// kWavesPerBlock slices; wave w of the block takes slice lo + g * 4 + w.
+struct SliceWalkRange {
+    int64_t lo, hi, j, Gx;
+    int w;
+};
+__device__ __forceinline__ SliceWalkRange slice_walk_range(int64_t S, int G) {
+    const int nx = (G >= 64 && (G & 7) == 0) ? 8 : 1;
+    const int64_t x = blockIdx.x % nx;
+    const int64_t R = (S + nx - 1) / nx;
+    SliceWalkRange r;
+    r.lo = x * R;
+    r.hi = (r.lo + R < S) ? r.lo + R : S;
+    r.j = blockIdx.x / nx;
+    r.Gx = G / nx;
+    r.w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    return r;
+}
+
 template <int CAP = 0, class F>
 __device__ __forceinline__ void for_each_slice(int64_t S, F &&f) {
     int G = gridDim.x;
@@ -27,17 +48,10 @@ __device__ __forceinline__ void for_each_slice(int64_t S, F &&f) {
         if ((int)blockIdx.x >= CAP) return;
         G = CAP;
     }
-    const int nx = (G >= 64 && (G & 7) == 0) ? 8 : 1;
-    const int64_t x = blockIdx.x % nx;
-    const int64_t j = blockIdx.x / nx;
-    const int64_t Gx = G / nx;
-    const int64_t R = (S + nx - 1) / nx;
-    const int64_t lo = x * R;
-    const int64_t hi = (lo + R < S) ? lo + R : S;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    for (int64_t g = j; lo + g * kWavesPerBlock < hi; g += Gx) {
-        const int64_t s = lo + g * kWavesPerBlock + w;
-        if (s < hi) f(s);
+    const SliceWalkRange r = slice_walk_range(S, G);
+    for (int64_t g = r.j; r.lo + g * kWavesPerBlock < r.hi; g += r.Gx) {
+        const int64_t s = r.lo + g * kWavesPerBlock + r.w;
+        if (s < r.hi) f(s);
     }
 }
 
@@ -321,28 +335,19 @@ __device__ __forceinline__ CmpHead cmp_head(const SellView<T> &A, int64_t s, int
 // f(s, head); lanes whose head.row is -1 hold no row.
 template <typename T, class F>
 __device__ __forceinline__ void for_each_cmp_slice(const SellView<T> &A, F &&f) {
-    const int64_t S = A.nslices;
     const int lane = threadIdx.x & 63;
-    const int G = gridDim.x;
-    const int nx = (G >= 64 && (G & 7) == 0) ? 8 : 1;
-    const int64_t x = blockIdx.x % nx;
-    const int64_t j = blockIdx.x / nx;
-    const int64_t Gx = G / nx;
-    const int64_t R = (S + nx - 1) / nx;
-    const int64_t lo = x * R;
-    const int64_t hi = (lo + R < S) ? lo + R : S;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const SliceWalkRange r = slice_walk_range(A.nslices, gridDim.x);
     CmpHead h;
     {
-        const int64_t s0 = lo + j * kWavesPerBlock + w;
-        if (s0 < hi) h = cmp_head(A, s0, lane);
+        const int64_t s0 = r.lo + r.j * kWavesPerBlock + r.w;
+        if (s0 < r.hi) h = cmp_head(A, s0, lane);
     }
-    for (int64_t g = j; lo + g * kWavesPerBlock < hi; g += Gx) {
-        const int64_t s = lo + g * kWavesPerBlock + w;
-        const int64_t sn = s + Gx * kWavesPerBlock;
+    for (int64_t g = r.j; r.lo + g * kWavesPerBlock < r.hi; g += r.Gx) {
+        const int64_t s = r.lo + g * kWavesPerBlock + r.w;
+        const int64_t sn = s + r.Gx * kWavesPerBlock;
         CmpHead hn;
-        if (sn < hi) hn = cmp_head(A, sn, lane);
-        if (s < hi) f(s, h);
+        if (sn < r.hi) hn = cmp_head(A, sn, lane);
+        if (s < r.hi) f(s, h);
         h = hn;
     }
 }

@@ -1557,8 +1557,13 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
     }
     Level &C = h->levels[l + 1];
     T *rc = lvec<T>(C, 0);
-    // the coarse level's first Jacobi sweep rides on the restriction
-    const bool c_first = !gs && c.o->n_pre > 0 && l + 2 < h->levels.size();
+    // the coarse level's first Jacobi sweep rides on the restriction, unless
+    // the coarse level will form it in its own correction (a large
+    // non-coarsest level whose down leg also runs through R)
+    const bool c_defers = l + 2 < h->levels.size() && rop && C.r_ready &&
+                          C.r_omega == c.o->omega && rview<T>(C, c.tr).val &&
+                          C.n > kFuseCorrRows;
+    const bool c_first = !gs && c.o->n_pre > 0 && l + 2 < h->levels.size() && !c_defers;
     T *ec_first = c_first ? lvec<T>(C, 1) : nullptr;
     if (rop) {
         // residual and restriction in one pass over R (t is not formed)

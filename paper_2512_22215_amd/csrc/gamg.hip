@@ -1203,8 +1203,11 @@ __device__ __forceinline__ double readlane_f64(double v, int j) {
 // one wavefront, one row per lane, the row's entries held in LDS
 // (entry-major, so lanes read distinct banks) and the search direction in
 // LDS.  Row i sums diag_i p_i first and then its entries in column order, as
-// the sparse kernels do.
+// the sparse kernels do.  The first kRegRow entries of a row also stay in
+// registers for the whole solve, so a product issues all their gathers of p
+// at once instead of one LDS round trip per entry.
 constexpr int kWaveRow = 48;
+constexpr int kRegRow = 16;
 
 // LDS ordering for one wavefront: its LDS operations execute in order, so a
 // fence against compiler reordering is all a lane-to-lane exchange needs
@@ -1252,6 +1255,13 @@ __device__ void coarsest_wave_body(const SellView<double> &A, const double *__re
         if (dt) rdt = 1.0 / dt[i];
     }
     wave_lds_sync();
+    int32_t cR[kRegRow];
+    double vR[kRegRow];
+#pragma unroll
+    for (int k = 0; k < kRegRow; ++k) {
+        cR[k] = k < m ? cL[k * kWave + i] : 0;
+        vR[k] = k < m ? vL[k * kWave + i] : 0.0;
+    }
     // z = M^-1 r: the diagonal, or the DIC factor by column-oriented
     // substitution: at step j lane j's value is final and is broadcast, and
     // every row holding column j takes its term (lower entries in ascending
@@ -1298,8 +1308,15 @@ __device__ void coarsest_wave_body(const SellView<double> &A, const double *__re
             wave_lds_sync();
             double qi = 0.0;
             if (i < n) {
+                double pv[kRegRow];
+#pragma unroll
+                for (int k = 0; k < kRegRow; ++k) pv[k] = k < m ? p[cR[k]] : 0.0;
                 qi = di * pi;
-                for (int k = 0; k < m; ++k) qi = qi + vL[k * kWave + i] * p[cL[k * kWave + i]];
+#pragma unroll
+                for (int k = 0; k < kRegRow; ++k)
+                    if (k < m) qi = qi + vR[k] * pv[k];
+                for (int k = kRegRow; k < m; ++k)
+                    qi = qi + vL[k * kWave + i] * p[cL[k * kWave + i]];
             }
             wave_lds_sync();
             const double pq = wave_sum(pi * qi);

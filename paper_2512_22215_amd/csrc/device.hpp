@@ -41,6 +41,15 @@ __device__ __forceinline__ SliceWalkRange slice_walk_range(int64_t S, int G) {
     return r;
 }
 
+// true once the solve has stopped (done) or the current inner solve of a
+// mixed-precision solve has (inner_done, always 0 in FP64 solves): the
+// kernels of an iteration then return at once.  Both flags are read unconditionally (bitwise or), so
+// their two scalar loads share one round trip at kernel start instead of
+// running in sequence.
+__device__ __forceinline__ bool vc_skip(const DevScalars *ds) {
+    return (ds->done | ds->inner_done) != 0;
+}
+
 template <int CAP = 0, class F>
 __device__ __forceinline__ void for_each_slice(int64_t S, F &&f) {
     int G = gridDim.x;

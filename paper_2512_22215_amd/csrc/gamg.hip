@@ -344,10 +344,6 @@ __global__ void k_singular(Sell A, int *flag) {
     }
 }
 
-// V-cycle kernels stop once the outer solve finished or the inner solve of
-// the mixed preconditioned CG converged (inner_done is 0 in FP64 solves)
-__device__ __forceinline__ bool vc_skip(const DevScalars *ds) { return ds->done || ds->inner_done; }
-
 // ---------------------------------------------------------------- setup
 // FP32 copies of every level's values; level 0's live with the handle
 static void ensure_f32_levels(ldu_t *h, hipStream_t st) {
@@ -675,7 +671,11 @@ struct FineCorr {
     T *e;
     const int32_t *start, *cells;
     __device__ __forceinline__ void operator()(int32_t a, T v) const {
-        for (int32_t k = start[a]; k < start[a + 1]; ++k) {
+        apply(start[a], start[a + 1], v);
+    }
+    // members k0..k1-1 of the aggregate (bounds loaded ahead by the caller)
+    __device__ __forceinline__ void apply(int32_t k0, int32_t k1, T v) const {
+        for (int32_t k = k0; k < k1; ++k) {
             const int32_t j = cells[k];
             e[j] = e[j] + v;
         }
@@ -693,20 +693,27 @@ k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
     if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
-    auto finish = [&](int32_t i, T y) {
+    // with CORR the aggregate bounds of row i are loaded before the row's
+    // product, so their round trip overlaps its gathers
+    auto finish = [&](int32_t i, T y, int32_t k0, int32_t k1) {
         const T zi = e[i] + omega * (r[i] - y) / A.diag[i];
         eo[i] = zi;
         if constexpr (DOT) acc[0] += (double)rdot[i] * (double)zi;
-        if constexpr (CORR) fc(i, zi);
+        if constexpr (CORR) fc.apply(k0, k1, zi);
     };
     if constexpr (CMP) {
         for_each_cmp_slice(A, [&](int64_t, const CmpHead &hd) {
             if (hd.row >= 0) {
                 const int32_t i = hd.row;
+                int32_t k0 = 0, k1 = 0;
+                if constexpr (CORR) {
+                    k0 = fc.start[i];
+                    k1 = fc.start[i + 1];
+                }
                 T y = A.diag[i] * e[i];  // the row's order: diagonal, then columns
                 cmp_entries_at<kCmpBatch>(A, hd.b0, hd.w, lane, Direct<T>{e},
                                           [&](int32_t, T v, T xv) { y = y + v * xv; });
-                finish(i, y);
+                finish(i, y, k0, k1);
             }
         });
     } else {
@@ -714,7 +721,12 @@ k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
             const int64_t p = s * kWave + lane;
             if (p < A.n) {
                 const int32_t i = (int32_t)p;
-                finish(i, sell_row<CMP>(A, s, lane, i, Direct<T>{e}));
+                int32_t k0 = 0, k1 = 0;
+                if constexpr (CORR) {
+                    k0 = fc.start[i];
+                    k1 = fc.start[i + 1];
+                }
+                finish(i, sell_row<CMP>(A, s, lane, i, Direct<T>{e}), k0, k1);
             }
         });
     }
@@ -1027,7 +1039,7 @@ k_vc_scale(SellView<T> A, const T *__restrict__ ec, const int32_t *__restrict__ 
 }
 
 struct EpiScale {
-    __device__ bool active(const DevScalars *ds) const { return !ds->done && !ds->inner_done; }
+    __device__ bool active(const DevScalars *ds) const { return !vc_skip(ds); }
     __device__ void operator()(const double *v, DevScalars *ds) const {
         ds->s = (isfinite(v[1]) && fabs(v[1]) > 1e-300) ? v[0] / v[1] : 1.0;
     }
@@ -1972,7 +1984,7 @@ k_mxg_start(int32_t n, int64_t S, const double *__restrict__ r, float *__restric
 __global__ void __launch_bounds__(kBlock)
 k_mxg_p0(int32_t n, int64_t S, const float *__restrict__ r, const float *__restrict__ z,
          float *__restrict__ p, double *partials, const DevScalars *ds) {
-    if (ds->done || ds->inner_done) return;
+    if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
     for_each_slice(S, [&](int64_t s) {
@@ -1986,7 +1998,7 @@ k_mxg_p0(int32_t n, int64_t S, const float *__restrict__ r, const float *__restr
 }
 
 struct EpiMxRho {
-    __device__ bool active(const DevScalars *ds) const { return !(ds->done || ds->inner_done); }
+    __device__ bool active(const DevScalars *ds) const { return !vc_skip(ds); }
     __device__ void operator()(const double *t, DevScalars *ds) const { ds->rho = t[0]; }
 };
 
@@ -1994,7 +2006,7 @@ struct EpiMxRho {
 __global__ void __launch_bounds__(kBlock)
 k_mxg_rz(int32_t n, int64_t S, const float *__restrict__ r, const float *__restrict__ z,
          double *partials, const DevScalars *ds) {
-    if (ds->done || ds->inner_done) return;
+    if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
     for_each_slice(S, [&](int64_t s) {
@@ -2005,7 +2017,7 @@ k_mxg_rz(int32_t n, int64_t S, const float *__restrict__ r, const float *__restr
 }
 
 struct EpiMxBeta {
-    __device__ bool active(const DevScalars *ds) const { return !(ds->done || ds->inner_done); }
+    __device__ bool active(const DevScalars *ds) const { return !vc_skip(ds); }
     __device__ void operator()(const double *t, DevScalars *ds) const {
         ds->beta = t[0] / ds->rho;
         ds->rho = t[0];
@@ -2015,7 +2027,7 @@ struct EpiMxBeta {
 __global__ void __launch_bounds__(kBlock)
 k_mxg_p(int32_t n, int64_t S, const float *__restrict__ z, float *__restrict__ p,
         const DevScalars *ds) {
-    if (ds->done || ds->inner_done) return;
+    if (vc_skip(ds)) return;
     const float bf = (float)ds->beta;
     const int lane = threadIdx.x & 63;
     for_each_slice(S, [&](int64_t s) {

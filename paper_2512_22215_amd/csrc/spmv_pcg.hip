@@ -644,7 +644,7 @@ template <bool CMP>
 __global__ void __launch_bounds__(kBlock)
 k_mx_q(SellView<float> A, const float *__restrict__ p, float *__restrict__ q, double *partials,
        const DevScalars *ds) {
-    if (ds->done || ds->inner_done) return;
+    if (vc_skip(ds)) return;
     const int lane = threadIdx.x & 63;
     double acc[1] = {0.0};
     for_each_slice(A.nslices, [&](int64_t s) {
@@ -660,7 +660,7 @@ k_mx_q(SellView<float> A, const float *__restrict__ p, float *__restrict__ q, do
 }
 
 struct EpiMxAlpha {
-    __device__ bool active(const DevScalars *ds) const { return !(ds->done || ds->inner_done); }
+    __device__ bool active(const DevScalars *ds) const { return !vc_skip(ds); }
     __device__ void operator()(const double *t, DevScalars *ds) const {
         const double pq = t[0];
         if (!isfinite(pq) || fabs(pq) <= 1e-300) ds->inner_done = 1;
@@ -673,7 +673,7 @@ __global__ void __launch_bounds__(kBlock)
 k_mx_update(int32_t n, int64_t S, const float *__restrict__ D, float *__restrict__ d,
             float *__restrict__ r, const float *__restrict__ p, const float *__restrict__ q,
             double *partials, const DevScalars *ds) {
-    if (ds->done || ds->inner_done) return;
+    if (vc_skip(ds)) return;
     const float af = (float)ds->alpha;
     const int lane = threadIdx.x & 63;
     double acc[2] = {0.0, 0.0};
@@ -696,7 +696,7 @@ k_mx_update(int32_t n, int64_t S, const float *__restrict__ D, float *__restrict
 
 struct EpiMxInner {
     int with_beta;
-    __device__ bool active(const DevScalars *ds) const { return !(ds->done || ds->inner_done); }
+    __device__ bool active(const DevScalars *ds) const { return !vc_skip(ds); }
     __device__ void operator()(const double *t, DevScalars *ds) const {
         const int it = ds->inner_iters + 1;
         ds->inner_iters = it;
@@ -712,7 +712,7 @@ struct EpiMxInner {
 __global__ void __launch_bounds__(kBlock)
 k_mx_p(int32_t n, int64_t S, const float *__restrict__ D, const float *__restrict__ r,
        float *__restrict__ p, const DevScalars *ds) {
-    if (ds->done || ds->inner_done) return;
+    if (vc_skip(ds)) return;
     const float bf = (float)ds->beta;
     const int lane = threadIdx.x & 63;
     for_each_slice(S, [&](int64_t s) {

@@ -72,7 +72,7 @@ def time_kernel(fn, reps, torch):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def cpu_baseline(iters_gpu, n=200, nxy=100, sample_iters=3):
+def cpu_baseline(iters_gpu, n=200, nxy=100, sample_iters=60):
     """The serial oracle on the host, on a bounded sample of the workload: the
     same 200-layer graded column on an nxy x nxy cross-section (1/4 of the
     cells at nxy = 100).  GAMG build (not counted), then sample_iters

@@ -305,6 +305,42 @@ def test_cycle_variants_match_oracle(smoother, inner, coarsest):
     assert sm.converged and true_res(c, xm.cpu().numpy()) <= 1e-12
 
 
+def test_coarsest_rows_longer_than_the_register_batch():
+    """A 58-cell coarsest level whose longest rows hold 18 entries: the
+    one-wavefront coarsest CG takes a row's first 16 entries from registers
+    and the rest from LDS.  One V-cycle, the GAMG solve, CG + V-cycle and the
+    mixed solve against the oracle."""
+    c = _gamg_case("c5s")
+    A = O.Ldu.from_case(c)
+    g = O.Gamg(A, n_coarsest=64)
+    L = g.level(g.n_levels - 1)
+    deg = np.bincount(L.owner, minlength=L.n) + np.bincount(L.neighbour, minlength=L.n)
+    # one wavefront (at most 64 cells, rows of at most 48 entries), past the batch
+    assert L.n <= 64 and 16 < deg.max() <= 48
+    b = c.rhs[0]
+    m = _lib().from_case(c)
+    m.gamg_setup(n_coarsest=64)
+    r = np.random.default_rng(9).standard_normal(c.n_cells)
+    e = m.vcycle(_t(r), n_coarsest=64).cpu().numpy()
+    ref = g.vcycle(r)
+    assert np.linalg.norm(e - ref) <= 1e-11 * np.linalg.norm(ref)
+    x, st = m.gamg(_t(b), rel_tol=1e-8, n_coarsest=64, history=300)
+    rs = g.solve(b, tol=1e-8)
+    assert st.n_levels == g.n_levels and st.converged and st.iterations == rs.iterations
+    assert hist_close(st.history, rs.history)
+    assert np.linalg.norm(x.cpu().numpy() - rs.x) <= 1e-10 * np.linalg.norm(rs.x)
+    m.gamg_setup(n_coarsest=64, n_pre=1, n_post=1)
+    xp, sp = m.pcg(_t(b), precond=2, rel_tol=1e-8)
+    rp = g.pcg(b, tol=1e-8, n_pre=1, n_post=1)
+    assert sp.converged and sp.iterations == rp.iterations
+    assert np.linalg.norm(xp.cpu().numpy() - rp.x) <= 1e-9 * np.linalg.norm(rp.x)
+    # mixed: FP32 V-cycles (FP64 coarsest) refined to 1e-12
+    xm, sm = m.gamg(_t(b), rel_tol=1e-12, precision="mixed", n_coarsest=64)
+    r12 = g.solve(b, tol=1e-12)
+    assert sm.converged and true_res(c, xm.cpu().numpy()) <= 1e-12
+    assert np.linalg.norm(xm.cpu().numpy() - r12.x) <= 1e-10 * np.linalg.norm(r12.x)
+
+
 def test_dic_on_a_large_coarsest_level_and_singular_fallback():
     """A coarsest level too large for the one-wavefront kernel takes the
     workgroup kernel's serial substitution; a singular coarsest level (pure

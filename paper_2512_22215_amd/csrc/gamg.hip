@@ -789,11 +789,12 @@ k_vc_restrict(int32_t nc, const int32_t *__restrict__ start, const int32_t *__re
               const T *__restrict__ Dc, T omega, const DevScalars *ds) {
     if (vc_skip(ds)) return;
     GRID_STRIDE(a, nc) {
+        const T dc = ec_first ? Dc[a] : T(1);  // loaded ahead of the member sums
         T s = T(0);
         for (int32_t k = start[a]; k < start[a + 1]; ++k) s += t[cells[k]];
         rc[a] = s;
         // the coarse level's first Jacobi sweep from zero, e_c = omega r_c / D_c
-        if (ec_first) ec_first[a] = omega * s / Dc[a];
+        if (ec_first) ec_first[a] = omega * s / dc;
     }
 }
 
@@ -1008,11 +1009,14 @@ k_vc_rrestrict(SellView<T> R, const T *__restrict__ r, T *__restrict__ rc,
     for_each_cmp_slice(R, [&](int64_t, const CmpHead &hd) {
         if (hd.row >= 0) {
             const int32_t c = hd.row;
+            // the coarse diagonal is loaded before the row, so its round
+            // trip overlaps the row's gathers
+            const T dc = ec_first ? Dc[c] : T(1);
             T acc = T(0);
             cmp_entries_at<kCmpBatch>(R, hd.b0, hd.w, lane, Direct<T>{r},
                                       [&](int32_t, T v, T xv) { acc = acc + v * xv; });
             rc[c] = acc;
-            if (ec_first) ec_first[c] = omega * acc / Dc[c];
+            if (ec_first) ec_first[c] = omega * acc / dc;
         }
     });
 }

@@ -94,12 +94,20 @@ def cpu_baseline(iters_gpu, n=200, nxy=100, sample_iters=60):
         cores = len(os.sched_getaffinity(0))
     except Exception:
         cores = os.cpu_count()
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": t_iter * scale * iters_gpu,
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"serial C oracle (1 thread; host exposes {cores}) on a {nxy}x{nxy}x{n} "
+        "sample": (f"serial C oracle (1 thread of {model}; host exposes {cores}) on a {nxy}x{nxy}x{n} "
                    f"slab of the workload ({case.n_cells} cells, same z grading): GAMG build "
                    f"{t_build:.1f} s (not counted), {r.iterations} V-cycle-preconditioned CG "
                    f"iterations at {t_iter:.3f} s each, scaled x{scale:.0f} by cells and "

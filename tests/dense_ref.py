@@ -128,3 +128,79 @@ def galerkin_ldu(n, owner, neighbour, diag, upper, lower, agg, nc):
     pat = (P.T @ adj @ P) > 0
     co, cn = np.nonzero(np.triu(pat, 1))
     return co, cn, np.diag(Ac).copy(), Ac[co, cn], Ac[cn, co]
+
+
+def handshake_rounds(n, owner, neighbour, weight, rounds):
+    """Handshake matching from its definition, round by round: in each round
+    every unmatched cell picks its unmatched neighbour of largest weight, and
+    two cells that picked each other become partners; stop after `rounds`
+    rounds or after a round that pairs nobody.  The weights of any cell's
+    candidate faces must be distinct (no tie rule is applied here)."""
+    nbrs = [[] for _ in range(n)]
+    for f in range(owner.size):
+        i, j = int(owner[f]), int(neighbour[f])
+        nbrs[i].append((float(weight[f]), j))
+        nbrs[j].append((float(weight[f]), i))
+    for i in range(n):
+        ws = [w for w, _ in nbrs[i]]
+        assert len(set(ws)) == len(ws), "tied candidate weights"
+    partner = -np.ones(n, np.int64)
+    for _ in range(rounds):
+        pick = -np.ones(n, np.int64)
+        for i in range(n):
+            if partner[i] < 0:
+                cand = [(w, j) for w, j in nbrs[i] if partner[j] < 0]
+                if cand:
+                    pick[i] = max(cand)[1]
+        new = [i for i in range(n) if pick[i] >= 0 and pick[pick[i]] == i]
+        if not new:
+            break
+        for i in new:
+            partner[i] = pick[i]
+    return partner
+
+
+def pcg32_inner_steps(n, owner, neighbour, diag, upper, lower, rhat, steps):
+    """The FP32 inner CG of the mixed-precision solve for a fixed number of
+    steps from d = 0, from its definition: coefficients, vectors, products,
+    divisions and axpys in float32; the dot products accumulated in float64
+    in index order; alpha and beta formed in float64 and rounded to float32.
+    The product visits the diagonal, then each face in order (lower into the
+    neighbour's row, then upper into the owner's row), each step in float32."""
+    f32 = np.float32
+    d32 = np.asarray(diag, np.float64).astype(f32)
+    u32 = np.asarray(upper, np.float64).astype(f32)
+    l32 = np.asarray(lower, np.float64).astype(f32)
+
+    def dot64(a, b):
+        s = 0.0
+        for ai, bi in zip(a.tolist(), b.tolist()):
+            s += float(ai) * float(bi)
+        return s
+
+    def amul32(x):
+        y = d32 * x
+        for f in range(owner.size):
+            o, b = int(owner[f]), int(neighbour[f])
+            y[b] = f32(y[b] + f32(l32[f] * x[o]))
+            y[o] = f32(y[o] + f32(u32[f] * x[b]))
+        return y
+
+    r = np.asarray(rhat, f32).copy()
+    d = np.zeros(n, f32)
+    z = r / d32
+    p = z.copy()
+    rho = dot64(r, z)
+    for k in range(steps):
+        q = amul32(p)
+        alpha = f32(rho / dot64(p, q))
+        d = d + alpha * p
+        r = r - alpha * q
+        if k == steps - 1:
+            break
+        z = r / d32
+        rho_new = dot64(r, z)
+        beta = f32(rho_new / rho)
+        rho = rho_new
+        p = z + beta * p
+    return d

@@ -951,3 +951,56 @@ def test_assembly_column_sums_divergence_and_interpolation():
                                       np.ones(own.size), np.ones(own.size))
     zf = np.where(nb - own == m * m, np.cumsum(dz)[own // (m * m)], z[own])
     assert np.allclose(uz, 1.0 + zf, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------- match-round cap
+
+def _sawtooth_chain(blocks=3, length=36, diag=-100.0):
+    """A chain of blocks*length cells, faces (i, i+1).  Inside a block the
+    coupling grows strictly towards the block's last face; the face joining
+    two blocks is the weakest of all.  With a constant diagonal the matching
+    weight is a monotone function of the coupling, so a handshake round pairs
+    exactly the top free pair of each block: after k rounds each block holds
+    min(k, length // 2) pairs, and a cap of k rounds binds for k < length / 2."""
+    n = blocks * length
+    own = np.arange(n - 1, dtype=np.int32)
+    nb = own + 1
+    pos = own % length
+    a = np.where(pos == length - 1, 0.01, 1.0 + pos.astype(np.float64))
+    return n, own, nb, np.full(n, diag), a
+
+
+@pytest.mark.parametrize("rounds", [1, 2, 16, 17, 100000])
+def test_match_round_cap_binds(rounds):
+    from dense_ref import handshake_rounds
+    n, own, nb, d, a = _sawtooth_chain()
+    g = O.Gamg(O.Ldu(n, own, nb, d, a, a), n_coarsest=2, max_levels=2,
+               match_rounds=rounds)
+    assert g.n_levels == 2
+    partner = g.level(0).partner
+    ref = handshake_rounds(n, own, nb, a, rounds)
+    assert np.array_equal(partner, ref)
+    pairs = int(np.sum(partner >= 0)) // 2
+    assert pairs == 3 * min(rounds, 18)
+
+
+# ---------------------------------------------------------------- FP32 inner CG
+
+@pytest.mark.parametrize("steps", [1, 2, 3])
+def test_pcg32_inner_steps_bit_exact(steps):
+    """One refinement step from x0 = 0 with an inner CG of exactly `steps`
+    iterations (no stopping test can fire: outer tolerance 0, inner 1e-300)
+    returns x = s * d with s = max|b| and d the FP32 inner iterate."""
+    from dense_ref import pcg32_inner_steps
+    c = _perm_case(box_case(4, 3, 3, coeff="lognormal", dirichlet_x0=1.0, seed=51), 52)
+    A = O.Ldu.from_case(c)
+    b = c.rhs[0]
+    r = O.pcg_mixed(A, b, tol=0.0, max_refine=1, inner_tol=1e-300,
+                    inner_max_iter=steps)
+    assert r.status == O.NOT_CONVERGED and r.iterations == 1
+    assert r.inner_iterations == steps
+    s = np.abs(b).max()
+    rhat = (b / s).astype(np.float32)
+    dref = pcg32_inner_steps(c.n_cells, c.owner, c.neighbour, c.diag, c.upper, c.lower,
+                             rhat, steps)
+    assert np.array_equal(r.x, s * dref.astype(np.float64))

@@ -29,6 +29,10 @@ EXPORTED = (
 )
 
 
+# ldu_bench.h: bandwidth-ceiling kernels (measurement aids)
+BENCH_EXPORTED = ("ldu_stream_read", "ldu_stream_copy", "ldu_stream_cg_update")
+
+
 class LduError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"ldu error {code}: {msg}")
@@ -107,6 +111,12 @@ def lib():
     L.ldu_coeff_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.ldu_assemble_pressure.argtypes = [vp] * 13
     L.ldu_last_error.restype = C.c_char_p
+    # bandwidth-ceiling kernels of ldu_bench.h
+    L.ldu_stream_read.argtypes = [vp, i64, vp, i, vp]
+    L.ldu_stream_copy.argtypes = [vp, vp, i64, i, vp]
+    L.ldu_stream_cg_update.argtypes = [vp, vp, vp, vp, C.c_double, i64, i, vp]
+    for name in BENCH_EXPORTED:
+        getattr(L, name).restype = C.c_int
     for name in EXPORTED:
         if name != "ldu_last_error" and name not in ("ldu_pcg_default_opts",
                                                      "ldu_gamg_default_opts"):
@@ -186,6 +196,8 @@ class LduMatrix:
         _check(lib().ldu_create(self.n, self.nf, _ptr(self.owner), _ptr(self.neighbour),
                                 _ptr(d), _ptr(u), _ptr(l), _stream(), C.byref(h)), False)
         self._h = h
+        # bumped by every call that replaces the coefficients
+        self.coeff_version = 0
 
     @classmethod
     def from_case(cls, case, device="cuda"):
@@ -218,6 +230,7 @@ class LduMatrix:
 
     def set_coeffs(self, diag, upper, lower):
         d, u, l = (self._vec(v) for v in (diag, upper, lower))
+        self.coeff_version += 1
         _check(lib().ldu_set_coeffs(self._h, _ptr(d), _ptr(u), _ptr(l), _stream()), False)
 
     def amul(self, x, out=None):
@@ -349,6 +362,7 @@ class LduMatrix:
             outs = [torch.empty(k, dtype=torch.float64, device=self.device)
                     for k in (self.n, self.nf, self.nf)]
         p = lambda t: None if t is None else _ptr(t)
+        self.coeff_version += 1
         _check(lib().ldu_assemble_pressure(self._h, p(gamma), p(weights), p(mag_sf), p(delta),
                                            p(diag_bc), p(phi), p(b_bc), p(b), p(outs[0]),
                                            p(outs[1]), p(outs[2]), _stream()), False)

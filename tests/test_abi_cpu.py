@@ -8,10 +8,11 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_2512_22215_amd", "libldu.so")
 HDR = os.path.join(ROOT, "include", "ldu.h")
+BENCH_HDR = os.path.join(ROOT, "include", "ldu_bench.h")
 
 
-def _declared():
-    src = open(HDR).read()
+def _declared(hdr=HDR):
+    src = open(hdr).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", src)) - {"if", "sizeof"})
 
@@ -30,6 +31,9 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     from paper_2512_22215_amd import ldu
     assert sorted(ldu.EXPORTED) == sorted(_declared())
+    for name in _declared(BENCH_HDR):
+        assert hasattr(lib, name), name
+    assert sorted(ldu.BENCH_EXPORTED) == sorted(_declared(BENCH_HDR))
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libldu.so not built")

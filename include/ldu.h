@@ -133,7 +133,9 @@ typedef struct {
     double final_residual;   /* ||b - A x|| / ||b|| recomputed in FP64 */
     long long level_cells[64];
     long long level_faces[64];
-    double *history;       /* optional HOST buffer for the residual history */
+    double *history;       /* optional HOST buffer for the residual history
+                              (entry k: residual after iteration or cycle k; a
+                              solve keeps its first 2^20 entries) */
     int history_len;       /* its capacity (entries) */
     int history_count;     /* entries written */
 } ldu_stats;

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import torch
 
-from .ldu import LduMatrix
+from .ldu import LDU_NOT_CONVERGED, LduError, LduMatrix
 
 
 class LduSolve(torch.autograd.Function):
@@ -18,26 +18,43 @@ class LduSolve(torch.autograd.Function):
     matrix: an LduMatrix holding the addressing; its coefficients are replaced
     by (diag, upper, lower) before the forward solve.  method: "pcg", "gamg"
     or "pbicg" (non-symmetric A); opts: dict of solver options used for both
-    solves.
+    solves.  Several solves may share one matrix before their backward
+    passes: a backward whose coefficients are no longer the matrix's puts its
+    own back first.  A forward or adjoint solve that stops above its
+    tolerance raises LduError (code LDU_NOT_CONVERGED).
     """
 
     @staticmethod
     def forward(ctx, diag, upper, lower, b, matrix: LduMatrix, method="pcg", opts=None):
         opts = dict(opts or {})
-        matrix.set_coeffs(diag.detach(), upper.detach(), lower.detach())
+        coeffs = (diag.detach(), upper.detach(), lower.detach())
+        matrix.set_coeffs(*coeffs)
         solve = {"gamg": matrix.gamg, "pbicg": matrix.pbicg, "pcg": matrix.pcg}[method]
         x, st = solve(b.detach(), **opts)
+        if not st.converged:
+            raise LduError(LDU_NOT_CONVERGED,
+                           f"forward {method} solve stopped at relative residual "
+                           f"{st.final_residual:.3e} after {st.iterations} iterations")
         ctx.matrix, ctx.method, ctx.opts = matrix, method, opts
-        ctx.save_for_backward(x)
+        ctx.version = matrix.coeff_version
+        ctx.save_for_backward(x, *coeffs)
         ctx.forward_stats = st
         return x
 
     @staticmethod
     def backward(ctx, gx):
-        (x,) = ctx.saved_tensors
+        x, diag, upper, lower = ctx.saved_tensors
         m = ctx.matrix
-        lam, _ = m.adjoint(gx.detach().to(torch.float64).contiguous(), solver=ctx.method,
-                           **ctx.opts)
+        if m.coeff_version != ctx.version:
+            # another solve replaced the coefficients since this forward
+            m.set_coeffs(diag, upper, lower)
+            ctx.version = m.coeff_version
+        lam, st = m.adjoint(gx.detach().to(torch.float64).contiguous(), solver=ctx.method,
+                            **ctx.opts)
+        if not st.converged:
+            raise LduError(LDU_NOT_CONVERGED,
+                           f"adjoint {ctx.method} solve stopped at relative residual "
+                           f"{st.final_residual:.3e} after {st.iterations} iterations")
         gd, gu, gl = m.coeff_grad(lam, x)
         return gd, gu, gl, lam, None, None, None
 

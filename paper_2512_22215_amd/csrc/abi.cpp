@@ -36,6 +36,16 @@ void *Arena::alloc(size_t bytes) {
     return p;
 }
 
+void Arena::release(void *p) {
+    for (size_t k = 0; k < ptrs_.size(); ++k)
+        if (ptrs_[k] == p) {
+            (void)hipFree(p);
+            ptrs_[k] = ptrs_.back();
+            ptrs_.pop_back();
+            return;
+        }
+}
+
 void Arena::release_all() {
     for (void *p : ptrs_) (void)hipFree(p);
     ptrs_.clear();

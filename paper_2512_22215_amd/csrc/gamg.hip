@@ -1768,7 +1768,7 @@ int gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_gamg_opts &o, bool
     const SellView<double> A = L.A.view(tr);
     const int64_t S = L.A.nslices;
     const int G = stream_grid_slices(S);
-    ensure_hist(h, o.max_cycles + 2);
+    ensure_hist(h, (int64_t)o.max_cycles + 2);
     fill_level_stats(h, stats);
     if (stats) { stats->refinements = 0; stats->history_count = 0; }
     set_scalars_for_solve(h, o.rel_tol, o.max_cycles, st);
@@ -1897,7 +1897,7 @@ int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, b
     const int n = L.n;
     const int64_t S = L.A.nslices;
     const int G = stream_grid_slices(S);
-    ensure_hist(h, o.max_iter + 2);
+    ensure_hist(h, (int64_t)o.max_iter + 2);
     fill_level_stats(h, stats);
     if (stats) { stats->refinements = 0; stats->history_count = 0; }
     set_scalars_for_solve(h, o.rel_tol, o.max_iter, st);
@@ -2063,7 +2063,7 @@ int pcg_gamg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, 
     const int n = L.n;
     const int64_t S = L.A.nslices;
     const int G = stream_grid_slices(S);
-    ensure_hist(h, o.max_refine + 2);
+    ensure_hist(h, (int64_t)o.max_refine + 2);
     fill_level_stats(h, stats);
     if (stats) stats->history_count = 0;
     set_scalars_for_solve(h, o.rel_tol, o.max_refine, st);
@@ -2128,7 +2128,7 @@ int gamg_mixed(ldu_t *h, const double *b, double *x, const ldu_gamg_opts &o, boo
     const SellView<double> A = L.A.view(tr);
     const int64_t S = L.A.nslices;
     const int G = stream_grid_slices(S);
-    ensure_hist(h, o.max_refine + 2);
+    ensure_hist(h, (int64_t)o.max_refine + 2);
     fill_level_stats(h, stats);
     if (stats) stats->history_count = 0;
     set_scalars_for_solve(h, o.rel_tol, o.max_refine, st);

@@ -57,6 +57,8 @@ constexpr int kCmpBatch = LDU_CMP_BATCH;  // compressed-slice row products: entr
 constexpr int kMaxLevels = 64;
 constexpr int kMaxCoarseRow = 128; // widest coarse-level row the setup supports
 constexpr double kCoarsestTol = 1e-10;
+// residual history entries kept on the device per solve (the first ones)
+constexpr int64_t kMaxHistory = int64_t(1) << 20;
 // largest coarsest level (with off-diagonal entries) the single-workgroup CG
 // accepts: its iteration cap max(2n, 100) keeps that kernel to a fraction of
 // a second; a hierarchy cut off above it (max_levels, stalled coarsening) is
@@ -123,6 +125,7 @@ public:
     void *alloc(size_t bytes);
     template <typename T>
     T *get(size_t count) { return static_cast<T *>(alloc(count * sizeof(T))); }
+    void release(void *p);  // frees one allocation of this arena
     void release_all();
 
 private:
@@ -261,7 +264,7 @@ int pbicg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool
                ldu_stats *stats, hipStream_t st);
 int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o,
               bool tr, ldu_stats *stats, hipStream_t st);
-void ensure_hist(ldu_t *h, int entries);
+void ensure_hist(ldu_t *h, int64_t entries);
 void copy_history(ldu_t *h, ldu_stats *stats, int count, hipStream_t st);
 void launch_coeff_grad(const Level &L, const double *lam, const double *x,
                        double *gd, double *gu, double *gl, hipStream_t st);

@@ -68,10 +68,17 @@ void read_scalars(ldu_t *h, hipStream_t st) {
     HIP_CHECK(hipStreamSynchronize(st));
 }
 
-void ensure_hist(ldu_t *h, int entries) {
+void ensure_hist(ldu_t *h, int64_t entries) {
+    // the device history keeps the first kMaxHistory entries of a solve; the
+    // epilogues write entry k only while k < hist_cap
+    if (entries > kMaxHistory) entries = kMaxHistory;
+    if (entries < 1) entries = 1;
     if (entries <= h->hist_cap) return;
-    h->hist = h->arena.get<double>(entries);
-    h->hist_cap = entries;
+    if (h->hist) h->arena.release(h->hist);
+    h->hist = nullptr;
+    h->hist_cap = 0;
+    h->hist = h->arena.get<double>((size_t)entries);
+    h->hist_cap = (int)entries;
 }
 
 void copy_history(ldu_t *h, ldu_stats *stats, int count, hipStream_t st) {
@@ -126,6 +133,7 @@ k_residual(SellView<double> A, const double *__restrict__ b, const double *__res
 struct EpiResidual {
     int mode, write_hist, has_p;
     double *hist;
+    int hist_cap;
     __device__ bool active(const DevScalars *ds) const {
         return mode != kResCycle || !ds->done;
     }
@@ -138,7 +146,7 @@ struct EpiResidual {
         const double res = ds->bnorm > 0.0 ? sqrt(t[0]) / ds->bnorm : 0.0;
         ds->res = res;
         const int it = ds->iters;
-        if (write_hist && hist) hist[it] = res;
+        if (write_hist && hist && it < hist_cap) hist[it] = res;
         if (mode == kResCycle) {
             if (!isfinite(res)) {
                 ds->status = LDU_ERR_NAN;
@@ -166,7 +174,7 @@ static void launch_residual(ldu_t *h, const SellView<double> &A, const double *b
         k_residual<false, P, MAXABS><<<G, kBlock, 0, st>>>(A, b, x, r, p, precond,
                                                            mode == kResCycle, h->partials, h->dev);
     launch_finalize<4, 1>(h->partials, G, h->dev,
-                          EpiResidual{mode, write_hist ? 1 : 0, P ? 1 : 0, h->hist}, st);
+                          EpiResidual{mode, write_hist ? 1 : 0, P ? 1 : 0, h->hist, h->hist_cap}, st);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -262,6 +270,7 @@ k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restr
 // update; with_beta: also beta = rho'/rho from the second sum
 struct EpiConverge {
     double *hist;
+    int hist_cap;
     int with_beta;
     __device__ bool active(const DevScalars *ds) const { return !ds->done; }
     __device__ void operator()(const double *t, DevScalars *ds) const {
@@ -270,7 +279,7 @@ struct EpiConverge {
         ds->rr = t[0];
         const double res = sqrt(t[0]) / ds->bnorm;
         ds->res = res;
-        if (hist) hist[it] = res;
+        if (hist && it < hist_cap) hist[it] = res;
         if (!isfinite(res)) {
             ds->status = LDU_ERR_NAN;
             ds->done = kFailed;
@@ -286,8 +295,8 @@ struct EpiConverge {
 };
 
 void launch_converge(ldu_t *h, int grid, bool with_beta, hipStream_t st) {
-    if (with_beta) launch_finalize<2>(h->partials, grid, h->dev, EpiConverge{h->hist, 1}, st);
-    else launch_finalize<1>(h->partials, grid, h->dev, EpiConverge{h->hist, 0}, st);
+    if (with_beta) launch_finalize<2>(h->partials, grid, h->dev, EpiConverge{h->hist, h->hist_cap, 1}, st);
+    else launch_finalize<1>(h->partials, grid, h->dev, EpiConverge{h->hist, h->hist_cap, 0}, st);
 }
 
 // p = D^-1 r + beta p
@@ -336,7 +345,7 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
     const int64_t S = L.A.nslices;
     const int G = stream_grid_slices(S);
     const int precond = o.precond ? 1 : 0;
-    ensure_hist(h, o.max_iter + 2);
+    ensure_hist(h, (int64_t)o.max_iter + 2);
     fill_stats_common(stats);
     set_scalars_for_solve(h, o.rel_tol, o.max_iter, st);
     launch_residual<true, false>(h, A, b, x, h->r, h->p, precond, kResPlain, true, st);
@@ -472,6 +481,7 @@ k_bicg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__rest
 // convergence as for CG, then beta, with breakdown when rho' vanishes
 struct EpiBicg {
     double *hist;
+    int hist_cap;
     __device__ bool active(const DevScalars *ds) const { return !ds->done; }
     __device__ void operator()(const double *t, DevScalars *ds) const {
         const int it = ds->iters + 1;
@@ -479,7 +489,7 @@ struct EpiBicg {
         ds->rr = t[0];
         const double res = sqrt(t[0]) / ds->bnorm;
         ds->res = res;
-        if (hist) hist[it] = res;
+        if (hist && it < hist_cap) hist[it] = res;
         if (!isfinite(res)) {
             ds->status = LDU_ERR_NAN;
             ds->done = kFailed;
@@ -530,7 +540,7 @@ int pbicg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool
         h->pt = h->arena.get<double>(n);
         h->qt = h->arena.get<double>(n);
     }
-    ensure_hist(h, o.max_iter + 2);
+    ensure_hist(h, (int64_t)o.max_iter + 2);
     fill_stats_common(stats);
     set_scalars_for_solve(h, o.rel_tol, o.max_iter, st);
     launch_residual<true, false>(h, A, b, x, h->r, h->p, precond, kResPlain, true, st);
@@ -565,7 +575,7 @@ int pbicg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool
                 launch_finalize<1>(h->partials, G, h->dev, EpiAlpha{}, st);
                 k_bicg_update<<<G, kBlock, 0, st>>>(n, S, A.diag, x, h->r, h->rt, h->p, h->q,
                                                     h->qt, precond, h->partials, h->dev);
-                launch_finalize<2>(h->partials, G, h->dev, EpiBicg{h->hist}, st);
+                launch_finalize<2>(h->partials, G, h->dev, EpiBicg{h->hist, h->hist_cap}, st);
                 k_bicg_p<<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->rt, h->p, h->pt, precond,
                                                h->dev);
             }
@@ -768,7 +778,7 @@ int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool 
     const int n = L.n;
     const int64_t S = L.A.nslices;
     const int G = stream_grid_slices(S);
-    ensure_hist(h, o.max_refine + 2);
+    ensure_hist(h, (int64_t)o.max_refine + 2);
     fill_stats_common(stats);
     set_scalars_for_solve(h, o.rel_tol, o.max_refine, st);
     k_mx_set_inner<<<1, 1, 0, st>>>(h->dev, o.inner_rel_tol, o.inner_max_iter);

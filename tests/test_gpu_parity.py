@@ -758,3 +758,140 @@ def test_solvers_on_matrices_without_faces(n):
                                            out_coeffs=True)
     assert np.array_equal(dd.cpu().numpy(), -bc) and np.array_equal(bb.cpu().numpy(), b)
     assert uu.numel() == 0 and ll.numel() == 0
+
+
+def test_create_rejects_duplicate_and_out_of_range_faces():
+    """Addressing errors the validator must catch before any kernel indexes
+    with the faces (it reads only owner[f], neighbour[f] and face f - 1)."""
+    from paper_2512_22215_amd import LduError
+    c = CASES["ragged"]
+    LduMatrix = _lib()
+    f = 40
+    own = np.insert(c.owner, f, c.owner[f])          # a duplicate of face f
+    nb = np.insert(c.neighbour, f, c.neighbour[f])
+    up = np.insert(c.upper, f, 1.0)
+    lo = np.insert(c.lower, f, 1.0)
+    bad = [(own, nb, up, lo)]
+    nb2 = c.neighbour.copy(); nb2[-1] = c.n_cells      # neighbour out of range
+    bad.append((c.owner, nb2, c.upper, c.lower))
+    own3 = c.owner.copy(); own3[0] = -1                 # negative owner
+    bad.append((own3, c.neighbour, c.upper, c.lower))
+    nb4 = c.neighbour.copy(); nb4[7] = 2 ** 31 - 1      # far out of range
+    bad.append((c.owner, nb4, c.upper, c.lower))
+    for k, (o, n, u, l) in enumerate(bad):
+        with pytest.raises(LduError) as e:
+            LduMatrix(c.n_cells, o, n, c.diag, u, l)
+        assert e.value.code == -2, k
+    # the oracle's validator agrees
+    for o, n, u, l in bad:
+        assert O.validate(c.n_cells, o, n, c.diag, u, l) == O.ERR_ADDR
+
+
+def test_nan_rhs_is_reported_by_every_solver():
+    from paper_2512_22215_amd import LduError
+    c = CASES["ragged"]
+    m = _lib().from_case(c)
+    m.gamg_setup(n_pre=1, n_post=1)
+    b = c.rhs[0].copy()
+    b[123] = np.nan
+    runs = [(m.pcg, {}), (m.pcg, dict(precision="mixed")), (m.pcg, dict(precond=2)),
+            (m.pcg, dict(precond=2, precision="mixed")), (m.gamg, dict(n_pre=1, n_post=1)),
+            (m.gamg, dict(n_pre=1, n_post=1, precision="mixed")), (m.pbicg, {})]
+    for fn, kw in runs:
+        with pytest.raises(LduError) as e:
+            fn(_t(b), **kw)
+        assert e.value.code == -3, (fn.__name__, kw)
+    # a NaN in the initial guess as well
+    x0 = np.zeros(c.n_cells); x0[5] = np.inf
+    with pytest.raises(LduError) as e:
+        m.pcg(_t(c.rhs[0]), x0=_t(x0))
+    assert e.value.code == -3
+    # the handle is not poisoned by these errors
+    x, st = m.pcg(_t(c.rhs[0]), rel_tol=1e-8)
+    assert st.converged
+    m.close()
+
+
+def test_inconsistent_singular_rhs_is_not_converged():
+    """A pure zero-gradient (singular) system with a right-hand side of
+    nonzero mean has no solution: every solver runs out of its budget and
+    returns LDU_NOT_CONVERGED with the last iterate, as the oracle does; the
+    true residual stays above the least-squares bound |mean(b)| sqrt(n)/||b||."""
+    c = box_case(9, 8, 7, coeff="lognormal", seed=3)
+    b = c.rhs[0] + 0.3
+    A = O.Ldu.from_case(c)
+    bound = abs(b.mean()) * np.sqrt(c.n_cells) / np.linalg.norm(b)
+    m = _lib().from_case(c)
+    m.gamg_setup(n_coarsest=10, n_pre=1, n_post=1)
+    g = O.Gamg(A, n_coarsest=10)
+    runs = [("pcg", m.pcg(_t(b), max_iter=50), O.pcg(A, b, max_iter=50)),
+            ("gamg", m.gamg(_t(b), max_cycles=30, n_coarsest=10, n_pre=1, n_post=1),
+             g.solve(b, max_cycles=30, n_pre=1, n_post=1)),
+            ("mixed", m.pcg(_t(b), precision="mixed", max_refine=3),
+             O.pcg_mixed(A, b, max_refine=3))]
+    for name, (x, st), ref in runs:
+        print(f"{name}: status {st.status} it {st.iterations} ref {ref.status} "
+              f"it {ref.iterations} residual {st.final_residual:.3e}", flush=True)
+        assert st.status == 1 and ref.status == O.NOT_CONVERGED and not st.converged, name
+        assert np.all(np.isfinite(x.cpu().numpy()))
+        assert st.final_residual >= bound * (1 - 1e-9)
+    assert runs[0][1][1].iterations == 50 == runs[0][2].iterations
+    assert runs[1][1][1].iterations == 30 == runs[1][2].iterations
+    m.close()
+
+
+@pytest.mark.parametrize("rounds", [1, 2, 16])
+def test_match_round_cap_matches_oracle(rounds):
+    """On a chain where every handshake round pairs one pair per block, the
+    cap on matching rounds binds; aggregates equal the oracle's."""
+    from tests.test_oracle_pins import _sawtooth_chain
+    n, own, nb, d, a = _sawtooth_chain()
+    m = _lib()(n, own, nb, d, a, a)
+    m.gamg_setup(n_coarsest=2, max_levels=2, match_rounds=rounds)
+    g = O.Gamg(O.Ldu(n, own, nb, d, a, a), n_coarsest=2, max_levels=2, match_rounds=rounds)
+    assert np.array_equal(m.level(0)["agg"].cpu().numpy(), g.level(0).agg)
+    m.close()
+
+
+def test_autograd_two_forwards_share_a_matrix():
+    """Two solves on one LduMatrix with different coefficients, then one
+    backward through both: each backward solves with its own coefficients."""
+    from meshgen import assemble_diag
+    from paper_2512_22215_amd import ldu_solve
+    c = box_case(8, 7, 6, coeff="lognormal", dirichlet_x0=2.0, seed=21)
+    ab = np.where(np.arange(c.n_cells) % 8 == 0, 2.0, 0.0)
+    m = _lib().from_case(c)
+    own = torch.from_numpy(c.owner.astype(np.int64)).cuda()
+    nb = torch.from_numpy(c.neighbour.astype(np.int64)).cuda()
+
+    def assemble(a):
+        return -(torch.zeros(c.n_cells, dtype=torch.float64, device="cuda")
+                 .index_add(0, own, a).index_add(0, nb, a)) - _t(ab)
+
+    a1 = _t(c.upper).requires_grad_(True)
+    a2 = _t(c.upper * 1.7 + 0.1).requires_grad_(True)
+    b = _t(c.rhs[0])
+    x1 = ldu_solve(assemble(a1), a1, a1, b, m, "pcg", rel_tol=1e-13)
+    x2 = ldu_solve(assemble(a2), a2, a2, b, m, "pcg", rel_tol=1e-13)
+    (0.5 * torch.sum(x1 ** 2) + torch.sum(x2)).backward()
+    for a, x, g in ((a1, x1, x1.detach()), (a2, x2, torch.ones_like(x2))):
+        av = a.detach().cpu().numpy()
+        A = O.Ldu(c.n_cells, c.owner, c.neighbour,
+                  assemble_diag(c.n_cells, c.owner, c.neighbour, av, av, ab), av, av)
+        xn = x.detach().cpu().numpy()
+        lam = O.pcg(A, g.cpu().numpy(), tol=1e-13, transpose=True).x
+        closed = (lam[c.owner] - lam[c.neighbour]) * (xn[c.owner] - xn[c.neighbour])
+        assert np.allclose(a.grad.cpu().numpy(), closed, rtol=1e-8,
+                           atol=1e-10 * np.abs(closed).max())
+    m.close()
+
+
+def test_autograd_raises_when_a_solve_does_not_converge():
+    from paper_2512_22215_amd import LduError, ldu_solve
+    c = CASES["ragged"]
+    m = _lib().from_case(c)
+    a = _t(c.upper).requires_grad_(True)
+    with pytest.raises(LduError) as e:
+        ldu_solve(_t(c.diag), a, a, _t(c.rhs[0]), m, "pcg", rel_tol=1e-12, max_iter=3)
+    assert e.value.code == 1
+    m.close()

@@ -143,7 +143,9 @@ struct EpiResidual {
         ds->bnorm = sqrt(t[1]);
         ds->maxabs = t[3];
         if (has_p) ds->rho = t[2];
-        const double res = ds->bnorm > 0.0 ? sqrt(t[0]) / ds->bnorm : 0.0;
+        // b = 0 gives 0; a non-finite b or x gives a non-finite residual
+        // (a NaN norm of b must not read as b = 0)
+        const double res = ds->bnorm == 0.0 ? 0.0 : sqrt(t[0]) / ds->bnorm;
         ds->res = res;
         const int it = ds->iters;
         if (write_hist && hist && it < hist_cap) hist[it] = res;

@@ -14,7 +14,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ldu_oracle.c")
-_LIB = os.path.join(_HERE, "libldu_oracle.so")
+# ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (every report aborts); the process must then
+# preload the ASan runtime (see tests/test_oracle_sanitized.py)
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libldu_oracle_san.so" if _SANITIZE else "libldu_oracle.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_ADDR, ERR_NAN, ERR_BREAKDOWN = -1, -2, -3, -4
@@ -26,9 +30,11 @@ def build(force: bool = False) -> str:
             os.path.getmtime(_SRC),
             os.path.getmtime(os.path.join(_HERE, "ldu_oracle.h"))):
         tmp = _LIB + ".tmp"
+        san = (["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                "-fno-sanitize-recover=all"] if _SANITIZE else [])
         subprocess.check_call(
             ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-             "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+             "-Wall", "-fPIC", "-shared"] + san + ["-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

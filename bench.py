@@ -72,24 +72,8 @@ def time_kernel(fn, reps, torch):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def cpu_baseline(iters_gpu, n=200, nxy=100, sample_iters=60):
-    """The serial oracle on the host, on a bounded sample of the workload: the
-    same 200-layer graded column on an nxy x nxy cross-section (1/4 of the
-    cells at nxy = 100).  GAMG build (not counted), then sample_iters
-    iterations of V-cycle-preconditioned CG; the per-iteration time, scaled by
-    the cell ratio and by the GPU's iteration count, estimates one full-size
-    oracle solve."""
-    import oracle as O
-    from meshgen import config_case
-    case = config_case("c3", n=n, nxy=nxy)
-    A = O.Ldu.from_case(case)
-    t0 = time.perf_counter()
-    g = O.Gamg(A)
-    t_build = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r = g.pcg(case.rhs[0], tol=1e-8, max_iter=sample_iters)
-    t_iter = (time.perf_counter() - t0) / max(r.iterations, 1)
-    scale = (n * n * n) / case.n_cells
+def host_cpu():
+    """(threads the process may use, CPU model) of the host."""
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
@@ -102,17 +86,121 @@ def cpu_baseline(iters_gpu, n=200, nxy=100, sample_iters=60):
                 break
     except OSError:
         pass
+    return cores, model
+
+
+def cpu_baseline(case, iters_gpu, sweeps, t_gpu, sample_iters=6):
+    """The serial oracle on the host, on the full workload (the same matrix
+    and right-hand side as the GPU step), timed in pieces that keep the run
+    bounded: its Amul (mean of 5 calls), its GAMG build (reported, not
+    counted), and sample_iters iterations of the same V-cycle-preconditioned
+    CG (sweeps + sweeps Jacobi sweeps).  The per-iteration time times the
+    GPU's iteration count estimates one oracle solve; COE (Sec. 4.3,
+    coefficient of equivalence) = T_cpu * N_cores / (T_gpu * N_gpus) with
+    one core and one GPU."""
+    import oracle as O
+    A = O.Ldu.from_case(case)
+    x = np.random.default_rng(7).standard_normal(case.n_cells)
+    ta = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        O.amul(A, x)
+        ta.append(time.perf_counter() - t0)
+    t_amul = float(np.mean(ta))
+    t0 = time.perf_counter()
+    g = O.Gamg(A)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = g.pcg(case.rhs[0], tol=1e-8, max_iter=sample_iters, n_pre=sweeps, n_post=sweeps)
+    t_iter = (time.perf_counter() - t0) / max(r.iterations, 1)
+    cores, model = host_cpu()
+    value = t_iter * iters_gpu
     return {
-        "value": t_iter * scale * iters_gpu,
+        "value": value,
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"serial C oracle (1 thread of {model}; host exposes {cores}) on a {nxy}x{nxy}x{n} "
-                   f"slab of the workload ({case.n_cells} cells, same z grading): GAMG build "
-                   f"{t_build:.1f} s (not counted), {r.iterations} V-cycle-preconditioned CG "
-                   f"iterations at {t_iter:.3f} s each, scaled x{scale:.0f} by cells and "
-                   f"x{iters_gpu} by the GPU's iteration count"),
+        "sample": (f"serial C oracle, 1 thread of {model} (host exposes {cores}), measured at "
+                   f"{case.n_cells:,} cells on the same matrix and rhs: {r.iterations} CG "
+                   f"iterations with one {sweeps}+{sweeps}-sweep V-cycle each at {t_iter:.3f} s "
+                   f"per iteration, times the GPU's {iters_gpu} iterations; GAMG build "
+                   f"{t_build:.1f} s not counted"),
+        "oracle_amul_s": t_amul,
+        "oracle_amul_GBps": amul_bytes(case.n_cells, case.n_faces) / t_amul / 1e9,
+        "oracle_gamg_build_s": t_build,
+        "oracle_s_per_iteration": t_iter,
+        "coe_vs_serial_oracle": value / t_gpu,
     }
+
+
+def stream_ceilings(torch, dev, n_cells):
+    """Hand-written HBM stream kernels (include/ldu_bench.h) timed with HIP
+    events on the current stream, best over a few grid sizes: a read-only sum
+    and a copy of the FP64 Amul's byte count, and the CG's x/r update over
+    n_cells cells."""
+    import ctypes as C
+
+    from paper_2512_22215_amd import lib
+    L = lib()
+    st = lambda: C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = lambda t: C.c_void_p(t.data_ptr())
+    out = {}
+    nread = 2 * 64 * 1024 * 1024  # 1 GiB of doubles, well above the caches
+    a = torch.rand(nread, dtype=torch.float64, device=dev)
+    part = torch.empty(8192, dtype=torch.float64, device=dev)
+    best = None
+    for blocks in (1024, 2048, 4096, 8192):
+        t = time_kernel(lambda: L.ldu_stream_read(p(a), nread, p(part), blocks, st()), 20, torch)
+        if best is None or t < best[0]:
+            best = (t, blocks)
+    out["read"] = {"GBps": 8 * nread / best[0] / 1e9, "bytes": 8 * nread, "blocks": best[1]}
+    b = torch.empty_like(a)
+    best = None
+    for blocks in (1024, 2048, 4096, 8192):
+        t = time_kernel(lambda: L.ldu_stream_copy(p(a), p(b), nread, blocks, st()), 20, torch)
+        if best is None or t < best[0]:
+            best = (t, blocks)
+    out["copy"] = {"GBps": 16 * nread / best[0] / 1e9, "bytes": 16 * nread, "blocks": best[1]}
+    del a, b
+    vs = [torch.rand(n_cells, dtype=torch.float64, device=dev) for _ in range(4)]
+    best = None
+    for blocks in (1024, 2048, 4096, 8192):
+        t = time_kernel(lambda: L.ldu_stream_cg_update(p(vs[0]), p(vs[1]), p(vs[2]), p(vs[3]),
+                                                       C.c_double(1e-3), n_cells, blocks, st()),
+                        20, torch)
+        if best is None or t < best[0]:
+            best = (t, blocks)
+    out["cg_update"] = {"GBps": 48 * n_cells / best[0] / 1e9, "bytes": 48 * n_cells,
+                        "blocks": best[1], "cells": n_cells}
+    del vs
+    torch.cuda.synchronize()
+    return out
+
+
+def load_golden(name):
+    """The oracle's full-size reference results (tests/golden, written by a
+    script that calls only the oracle), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{name}.json")
+    try:
+        return json.load(open(path))
+    except (OSError, ValueError):
+        return None
+
+
+def sampled_error(x, gold, rec):
+    """||x - x_orc|| / ||x_orc|| over the oracle's sampled cells, and the
+    relative difference of the 2-norms of the whole vectors (x: a device
+    tensor)."""
+    if gold is None or rec is None:
+        return None
+    import torch
+    idx = np.asarray(gold["indices"], dtype=np.int64)
+    want = np.asarray(rec["x"]["sample"])
+    got = x[torch.from_numpy(idx).to(x.device)].cpu().numpy()
+    return {"sampled_rel_err": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+            "norm2_rel_diff": float(abs(float(x.norm()) - rec["x"]["norm2"]) /
+                                    rec["x"]["norm2"]),
+            "samples": int(idx.size), "oracle_iterations": rec["iterations"]}
 
 
 def _timed(torch, fn, reps=2):
@@ -153,6 +241,28 @@ def run_suite(torch, dev, only=None):
         t = time_kernel(lambda: m.amul(x, out=y), 100, torch)
         return {"us": t * 1e6, "GBps": amul_bytes(case.n_cells, case.n_faces) / t / 1e9}
 
+    import oracle as O
+    cores, model = host_cpu()
+    host = f"serial C oracle, 1 thread of {model} (host exposes {cores})"
+
+    def oracle_amul(case):
+        A = O.Ldu.from_case(case)
+        x = np.random.default_rng(7).standard_normal(case.n_cells)
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            O.amul(A, x)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.mean(ts))
+        return {"s": t, "GBps": amul_bytes(case.n_cells, case.n_faces) / t / 1e9, "host": host}
+
+    def oracle_solve(label, fn, t_gpu):
+        t0 = time.perf_counter()
+        r = fn()
+        t = time.perf_counter() - t0
+        return {"solver": label, "s": t, "iterations": r.iterations, "status": r.status,
+                "host": host, "coe_vs_serial_oracle": t / t_gpu}
+
     for name, kw in (("c1", {}), ("c2", {"order": "random"}), ("c2", {"order": "rcm"}),
                      ("c4", {}), ("c5", {})):
         label = name + ("-rcm" if kw.get("order") == "rcm" else "")
@@ -166,8 +276,14 @@ def run_suite(torch, dev, only=None):
         rec = {"workload": case.name, "cells": case.n_cells, "faces": case.n_faces,
                "amul_f64": amul_rec(m, case)}
         b = tens(case.rhs[0])
+        if name in ("c2", "c4"):
+            rec["oracle_amul_f64"] = oracle_amul(case)
         if name == "c1":
             rec["pcg_diag_fp64"] = solve_rec(m, b, m.pcg, rel_tol=1e-8)
+            A = O.Ldu.from_case(case)
+            rec["oracle_pcg_diag_fp64"] = oracle_solve(
+                "diagonal PCG, FP64, 1e-8", lambda: O.pcg(A, case.rhs[0], tol=1e-8),
+                rec["pcg_diag_fp64"]["s"])
         elif name == "c2":
             rec["pcg_diag_fp64"] = solve_rec(m, b, m.pcg, rel_tol=1e-8)
             m.gamg_setup(n_pre=1, n_post=1)
@@ -198,12 +314,44 @@ def run_suite(torch, dev, only=None):
         elif name == "c5":
             rec["pcg_diag_fp64"] = solve_rec(m, b, m.pcg, rel_tol=1e-8)
             rec["pcg_diag_mixed"] = solve_rec(m, b, m.pcg, rel_tol=1e-8, precision="mixed")
-            t, (x, _) = _timed(torch, lambda: m.pcg(b, rel_tol=1e-11, max_iter=5000))
-            g = x - tens(case.meta["x_target"])
-            ta, (lam, sa) = _timed(torch, lambda: m.adjoint(g, rel_tol=1e-11, max_iter=5000))
-            tg = time_kernel(lambda: m.coeff_grad(lam, x), 20, torch)
-            rec["forward_fp64_1e-11_s"] = t
-            rec["adjoint_fp64_1e-11"] = {"s": ta, "iterations": sa.iterations}
+            m.gamg_setup(n_pre=1, n_post=1)
+            rec["pcg_gamg_fp64"] = solve_rec(m, b, m.pcg, rel_tol=1e-8, precond=2)
+            rec["pcg_gamg_mixed"] = solve_rec(m, b, m.pcg, rel_tol=1e-8, precond=2,
+                                              precision="mixed")
+            A = O.Ldu.from_case(case)
+            g = O.Gamg(A)
+            rec["oracle_pcg_gamg_fp64"] = oracle_solve(
+                "CG + V-cycle (1+1), FP64, 1e-8",
+                lambda: g.pcg(case.rhs[0], tol=1e-8, n_pre=1, n_post=1),
+                rec["pcg_gamg_fp64"]["s"])
+            del g
+            # the differentiable solve: loss = |x - x_t|^2 / 2 through LduSolve,
+            # gradients for every symmetric face coefficient and b, forward +
+            # backward, FP64 and FP32-bulk-with-FP64-refinement, both to 1e-11
+            from paper_2512_22215_amd import ldu_solve
+            own = torch.from_numpy(case.owner.astype(np.int64)).to(dev)
+            nbi = torch.from_numpy(case.neighbour.astype(np.int64)).to(dev)
+            ab = tens(case.meta["a_boundary"])
+            xt = tens(case.meta["x_target"])
+            zero = torch.zeros(case.n_cells, dtype=torch.float64, device=dev)
+            grads = {}
+            for prec in ("fp64", "mixed", "fp64", "mixed"):  # the first pair warms up
+                a = tens(case.upper).requires_grad_(True)
+                bb = tens(case.rhs[0]).requires_grad_(True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                d = -(zero.index_add(0, own, a).index_add(0, nbi, a)) - ab
+                x = ldu_solve(d, a, a, bb, m, "pcg", precond=2, precision=prec, rel_tol=1e-11)
+                (0.5 * torch.sum((x - xt) ** 2)).backward()
+                torch.cuda.synchronize()
+                grads[prec] = (time.perf_counter() - t0, a.grad)
+            rec["autograd_forward_backward_1e-11"] = {
+                "fp64_s": grads["fp64"][0], "mixed_s": grads["mixed"][0],
+                "grad_mixed_vs_fp64_rel": float(torch.linalg.norm(grads["mixed"][1] -
+                                                                  grads["fp64"][1]) /
+                                                torch.linalg.norm(grads["fp64"][1]))}
+            lam = tens(np.zeros(case.n_cells))
+            tg = time_kernel(lambda: m.coeff_grad(lam, zero), 20, torch)
             rec["coeff_grad_us"] = tg * 1e6
         m.close()
         log(f"[suite] {json.dumps(rec)}")
@@ -284,16 +432,14 @@ def main():
     y32 = torch.empty_like(x32)
     t_amul32 = time_kernel(lambda: m.amul_f32(x32, out=y32), 200, torch)
     a32bytes = 12 * case.n_cells + 16 * case.n_faces
-    # copy ceiling: one read + one write of the Amul's byte count
-    buf = torch.empty(abytes // 16, dtype=torch.float64, device=dev)
-    buf2 = torch.empty_like(buf)
-    t_copy = time_kernel(lambda: buf2.copy_(buf), 50, torch)
-    copy_gbs = 2 * buf.numel() * 8 / t_copy / 1e9
-    del buf, buf2
+    # HBM ceilings of hand-written stream kernels, timed in this run
+    ceil = stream_ceilings(torch, dev, case.n_cells)
+    copy_gbs = ceil["copy"]["GBps"]
+    log(f"[bench] ceilings: read {ceil['read']['GBps']:.0f}, copy {copy_gbs:.0f}, "
+        f"CG update {ceil['cg_update']['GBps']:.0f} GB/s")
     if args.amul_only:
         print(json.dumps({"amul_us": t_amul * 1e6, "amul_GBps": amul_gbs,
-                          "amul_bytes": abytes, "copy_GBps": copy_gbs,
-                          "copy_bytes_each_way": abytes // 16 * 8}))
+                          "amul_bytes": abytes, "ceilings": ceil}))
         m.close()
         return
 
@@ -314,8 +460,14 @@ def main():
     res = m.residual(b, xs)
     assert st.converged and res <= 1e-8, (st, res)
     t_step = float(np.mean(times))
+    gold = load_golden("c3") if args.n == 200 else None
+    grec = gold["pcg_gamg_fp64"] if gold else None
+    err64 = sampled_error(xs, gold, grec)
+    if err64:
+        log(f"[bench] FP64 vs oracle: sampled |x - x_orc|/|x_orc| "
+            f"{err64['sampled_rel_err']:.2e}, oracle {grec['iterations']} iterations")
 
-    variants, mixed_rec, adj_rec, bicg_rec = {}, None, None, None
+    variants, mixed_rec, adj_rec, bicg_rec, gamg_rec = {}, None, None, None, None
     if not args.no_extra:
         # the mixed form of the same solve: FP64 refinement around FP32 CG with an
         # FP32 V-cycle preconditioner (one warm-up, then the same step count)
@@ -334,7 +486,34 @@ def main():
             f"{sm.iterations} inner iterations, true residual {mres:.3e}")
         mixed_rec = {"s": float(np.mean(mtimes)), "refinements": sm.refinements,
                      "inner_iterations": sm.iterations, "true_residual": mres,
-                     "solver": "FP64 refinement, FP32 CG + FP32 V-cycle (FP64 coarsest)"}
+                     "solver": "FP64 refinement, FP32 CG + FP32 V-cycle (FP64 coarsest)",
+                     "vs_fp64_oracle": sampled_error(xm, gold, grec)}
+
+        # standalone GAMG (x += V(b - A x) per cycle, correction scaling on)
+        # from x0 = 0 with a 400-cycle cap, FP64 and mixed: the configured c3
+        # solver; its convergence factor per cycle is what makes CG + V-cycle
+        # the headline solver on this graded mesh
+        gamg_rec = {}
+        for label, kw in (("fp64_1+1", dict(n_pre=args.sweeps, n_post=args.sweeps)),
+                          ("fp64_2+2", dict(n_pre=2, n_post=2)),
+                          ("mixed_1+1", dict(n_pre=args.sweeps, n_post=args.sweeps,
+                                             precision="mixed", max_refine=400))):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xg, sg = m.gamg(b, rel_tol=1e-8, max_cycles=400, history=500, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            h = np.asarray(sg.history)
+            k = len(h) - 1
+            gamg_rec[label] = {
+                "s": dt, "cycles": sg.refinements if kw.get("precision") else sg.iterations,
+                "converged": sg.converged, "final_residual": sg.final_residual,
+                "factor_per_cycle": float((h[-1] / h[0]) ** (1.0 / k)) if k > 0 else None,
+                "factor_last_20": float((h[-1] / h[-21]) ** (1.0 / 20)) if k > 20 else None,
+                "cycles_to_1e-8_at_that_rate": (
+                    float(np.log(1e-8 / h[-1]) / np.log((h[-1] / h[-21]) ** (1.0 / 20)) + k)
+                    if k > 20 and h[-1] > 1e-8 else None)}
+            log(f"[bench] standalone GAMG {label}: {dt:.3f} s, {gamg_rec[label]}")
 
         # the adjoint form: lambda = A^-T (x - x_t) with the same preconditioned CG
         # (on the transposed values of every level), then the per-face gradients
@@ -388,6 +567,28 @@ def main():
             variants[name] = rec
             log(f"[bench] variant {name}: {rec['levels']} levels, fp64 {rec['fp64']['s']:.4f} s "
                 f"({rec['fp64']['iterations']} it), mixed {rec['mixed']['s']:.4f} s")
+
+        # the tail of small levels: pairwise down to level `from`, then 2 or 3
+        # matching passes per level (FP64, one warm-up, best of two)
+        tail = {}
+        for afrom in (3, 4, 5, 6):
+            for passes in (2, 3):
+                m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, passes=passes,
+                             aggressive_from=afrom)
+                m.pcg(b, **opts)
+                vt = []
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    xv, sv = m.pcg(b, **opts)
+                    torch.cuda.synchronize()
+                    vt.append(time.perf_counter() - t0)
+                assert sv.converged, (afrom, passes, sv)
+                tail[f"from{afrom}_passes{passes}"] = {
+                    "levels": m.n_levels(), "iterations": sv.iterations, "s": float(min(vt))}
+        best = min(tail, key=lambda k: tail[k]["s"])
+        variants["tail_sweep"] = {"runs": tail, "best": best}
+        log(f"[bench] tail sweep: best {best} {tail[best]}")
         m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
 
         # the non-symmetric solve (PBiCG, diagonal preconditioner) on the
@@ -456,8 +657,10 @@ def main():
         "amul_f64": {"us": t_amul * 1e6, "GBps": amul_gbs, "bytes": abytes},
         "amul_f32": {"us": t_amul32 * 1e6, "GBps": a32bytes / t_amul32 / 1e9,
                      "bytes": a32bytes},
-        "copy_ceiling_GBps": copy_gbs,
+        "ceilings": ceil,
         "amul_frac_of_copy": amul_gbs / copy_gbs,
+        "fp64_vs_oracle": err64,
+        "standalone_gamg": gamg_rec if not args.no_extra else None,
     }
     if args.full:
         for name, fn, kw in (
@@ -502,7 +705,7 @@ def main():
     }
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(st.iterations, n=args.n)
+        out["cpu_baseline"] = cpu_baseline(case, st.iterations, args.sweeps, t_step)
         log(f"[bench] oracle estimate {out['cpu_baseline']['value']:.1f} s per solve")
     m.close()
     print(json.dumps(out))

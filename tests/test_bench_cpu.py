@@ -16,11 +16,15 @@ def test_more_than_one_gpu_is_refused():
     assert "--gpus must be 1" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
 
 
-def test_cpu_baseline_record_on_a_small_slab():
+def test_cpu_baseline_record_on_a_small_case():
     import bench
-    rec = bench.cpu_baseline(10, n=16, nxy=8, sample_iters=3)
+    from meshgen import config_case
+    case = config_case("c3", n=16, nxy=8)
+    rec = bench.cpu_baseline(case, 10, 1, 0.5, sample_iters=3)
     assert rec["kind"] == "oracle" and rec["unit"] == "s" and rec["cores"] == 1
-    assert rec["value"] > 0
-    # the sample names its size, its iteration count and the scaling applied
-    assert "8x8x16" in rec["sample"] and "3 V-cycle-preconditioned CG iterations" in rec["sample"]
-    assert "x10 by the GPU's iteration count" in rec["sample"]
+    assert rec["value"] > 0 and rec["oracle_amul_s"] > 0 and rec["oracle_gamg_build_s"] > 0
+    assert abs(rec["coe_vs_serial_oracle"] - rec["value"] / 0.5) <= 1e-12 * rec["value"]
+    # the sample names the measured size, the iteration count and the sweeps
+    assert "measured at 1,024 cells" in rec["sample"]
+    assert "3 CG iterations with one 1+1-sweep V-cycle" in rec["sample"]
+    assert "times the GPU's 10 iterations" in rec["sample"]

@@ -1,12 +1,19 @@
 """GPU parity at the full workload sizes, in the bench's launch configuration.
 
 c3: 200^3 graded hex (8M cells); c4: 256^3 RCM-ordered (16.7M cells), three
-right-hand sides back to back with warm starts; c5: 100^3 (1M cells),
-forward + adjoint.  The oracle recomputes what it can afford at these sizes:
-full Amul products (bit-exact), true residuals of every GPU solution, the
-level-0 agglomeration and Galerkin matrix, and the adjoint gradient; the rest
-is checked through properties (residual bounds, FP64-vs-mixed agreement).
+right-hand sides back to back with warm starts; c5: 100^3 (1M cells), the
+differentiable solve.  The oracle recomputes what it can afford here (full
+Amul products, bit-exact; the true residual of every GPU solution; the
+level-0 agglomeration and Galerkin matrix); the oracle's full-size solves,
+which take minutes on one core, come from tests/golden/fullsize_*.json
+(written by make_fullsize_golden.py, which calls only the oracle): iteration
+counts, residual histories and the solution at 4096 seeded cells.  Each test
+prints the error of every GPU result against the FP64 oracle.
 """
+import json
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -17,6 +24,8 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 torch = pytest.importorskip("torch")
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
 
 def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -24,6 +33,28 @@ def _t(a):
 
 def _res(A, b, x):
     return np.linalg.norm(b - O.amul(A, x)) / np.linalg.norm(b)
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"fullsize_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return json.load(open(path))
+
+
+def _vs_oracle(x, gold, rec):
+    """(sampled ||x - x_orc|| / ||x_orc||, relative difference of the 2-norms)"""
+    idx = torch.from_numpy(np.asarray(gold["indices"], dtype=np.int64)).cuda()
+    got = x[idx].cpu().numpy()
+    want = np.asarray(rec["x"]["sample"])
+    return (float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+            abs(float(x.norm()) - rec["x"]["norm2"]) / rec["x"]["norm2"])
+
+
+def _hist_rel(h, ref):
+    h, ref = np.asarray(h), np.asarray(ref)
+    n = min(h.size, ref.size)
+    return float(np.max(np.abs(h[:n] - ref[:n]) / ref[:n]))
 
 
 @pytest.fixture(scope="module")
@@ -53,22 +84,36 @@ def test_c3_amul_and_level0_hierarchy_bit_exact(c3):
 
 
 def test_c3_pressure_solve_fp64_and_mixed(c3):
+    """The headline solve (CG + V-cycle, 1 + 1 sweeps, FP64, to 1e-8 from
+    x0 = 0) against the oracle's full-size solve, and the mixed form against
+    the same FP64 oracle solution."""
     from paper_2512_22215_amd import LduMatrix
+    gold = _golden("c3")
+    rec = gold["pcg_gamg_fp64"]
     m = LduMatrix.from_case(c3)
     m.gamg_setup(n_pre=1, n_post=1)
+    assert [m.level(k)["n"] for k in range(m.n_levels())] == gold["levels"]
     A = O.Ldu.from_case(c3)
     b = c3.rhs[0]
-    x64, s64 = m.pcg(_t(b), precond=2, rel_tol=1e-8)
+    x64, s64 = m.pcg(_t(b), precond=2, rel_tol=1e-8, history=1000)
     xm, sm = m.pcg(_t(b), precond=2, rel_tol=1e-8, precision="mixed")
-    a64, am = x64.cpu().numpy(), xm.cpu().numpy()
-    assert s64.converged and _res(A, b, a64) <= 1e-8
-    assert sm.converged and _res(A, b, am) <= 1e-8
-    # both satisfy the residual bound; their difference is bounded by the
-    # solution error at 1e-8 (condition number times tolerance)
-    rel = np.linalg.norm(am - a64) / np.linalg.norm(a64)
-    print(f"c3: fp64 {s64.iterations} it, mixed {sm.refinements} refinements / "
-          f"{sm.iterations} inner it, |x_mixed - x_fp64| / |x_fp64| = {rel:.2e}")
-    assert rel <= 1e-3
+    e64, n64 = _vs_oracle(x64, gold, rec)
+    em, nm = _vs_oracle(xm, gold, rec)
+    hr = _hist_rel(s64.history, rec["history"])
+    print(f"c3 fp64: {s64.iterations} it (oracle {rec['iterations']}), history max rel "
+          f"diff {hr:.2e}, |x - x_orc|/|x_orc| sampled {e64:.2e}, norm diff {n64:.2e}")
+    print(f"c3 mixed: {sm.refinements} refinements / {sm.iterations} inner it, "
+          f"|x - x_orc|/|x_orc| sampled {em:.2e}, norm diff {nm:.2e}")
+    assert s64.converged and _res(A, b, x64.cpu().numpy()) <= 1e-8
+    assert sm.converged and _res(A, b, xm.cpu().numpy()) <= 1e-8
+    # same path as the oracle: equal count, the FP64 parity bars of the small
+    # cases (histories 1e-9, solutions 1e-10; measured 7e-13 and 3e-14)
+    assert s64.iterations == rec["iterations"]
+    assert len(s64.history) == len(rec["history"]) and hr <= 1e-9
+    assert e64 <= 1e-10 and n64 <= 1e-10
+    # the mixed solution is another solution at 1e-8 (its refinement stops at a
+    # true residual of 2.7e-9); measured 1.5e-8 from the FP64 oracle's
+    assert em <= 1e-6 and nm <= 1e-6
     # deterministic: a repeat is bitwise identical
     x2, _ = m.pcg(_t(b), precond=2, rel_tol=1e-8)
     assert torch.equal(x2, x64)
@@ -76,80 +121,114 @@ def test_c3_pressure_solve_fp64_and_mixed(c3):
 
 
 def test_c4_three_rhs_warm_started():
+    """Three right-hand sides back to back, each warm-started from the last
+    solution: CG + V-cycle and diagonal PCG in FP64 against the oracle's
+    full-size runs, and their mixed forms against the FP64 oracle solution."""
     from paper_2512_22215_amd import LduMatrix
+    gold = _golden("c4")
     c = config_case("c4")
     m = LduMatrix.from_case(c)
     A = O.Ldu.from_case(c)
     x = np.random.default_rng(8).standard_normal(c.n_cells)
     assert np.array_equal(m.amul(_t(x)).cpu().numpy(), O.amul(A, x))
     m.gamg_setup(n_pre=1, n_post=1)
-    for prec in ("fp64", "mixed"):
-        xk = torch.zeros(c.n_cells, dtype=torch.float64, device="cuda")
-        for k, b in enumerate(c.rhs):
-            xk, st = m.pcg(_t(b), x0=xk, precond=2, rel_tol=1e-8, precision=prec)
-            assert st.converged, (prec, k)
-            assert _res(A, b, xk.cpu().numpy()) <= 1e-8
-            print(f"c4 {prec} rhs {k}: initial residual {st.initial_residual:.3e}, "
-                  f"{st.iterations} it, {st.refinements} refinements")
+    for label, kw in (("pcg_gamg", dict(precond=2)), ("pcg_diag", dict(precond=1))):
+        for prec in ("fp64", "mixed"):
+            xk = torch.zeros(c.n_cells, dtype=torch.float64, device="cuda")
+            for k, b in enumerate(c.rhs):
+                rec = gold[f"{label}_fp64"][k]
+                xk, st = m.pcg(_t(b), x0=xk, rel_tol=1e-8, precision=prec, history=5000,
+                               **kw)
+                assert st.converged, (label, prec, k)
+                assert _res(A, b, xk.cpu().numpy()) <= 1e-8
+                e, nd = _vs_oracle(xk, gold, rec)
+                if prec == "fp64":
+                    hr = _hist_rel(st.history, rec["history"])
+                    print(f"c4 {label} fp64 rhs {k}: {st.iterations} it (oracle "
+                          f"{rec['iterations']}), history max rel diff {hr:.2e}, |x - x_orc|/"
+                          f"|x_orc| sampled {e:.2e}, norm diff {nd:.2e}")
+                    assert abs(st.iterations - rec["iterations"]) <= max(1, rec["iterations"] // 100)
+                    assert e <= 1e-6
+                else:
+                    print(f"c4 {label} mixed rhs {k}: {st.refinements} refinements / "
+                          f"{st.iterations} inner it, |x - x_orc|/|x_orc| sampled {e:.2e}, "
+                          f"norm diff {nd:.2e}")
+                    assert e <= 1e-3
     m.close()
 
 
-def test_c5_adjoint_gradient():
-    from meshgen import assemble_diag
-    from paper_2512_22215_amd import LduMatrix
+def test_c5_differentiable_solve_mixed_and_fp64():
+    """c5 as stated: loss = |x - x_t|^2 / 2 with x = A(c)^-1 b through the
+    autograd Function (LduSolve), FP32 bulk inside FP64 refinement (CG + FP32
+    V-cycle), forward and backward on the 1M-cell box; the gradients with
+    respect to every symmetric face coefficient c_f (upper = lower = c_f, each
+    end's diagonal -= c_f, assembled in torch) and to b.  Checked against the
+    oracle's adjoint gradient (4096 sampled faces, lambda at 4096 cells), and
+    against central finite differences at a relative step of about 1e-6 on
+    the 20 seeded faces, both from the oracle's full-size run.  The FP64 form runs beside
+    it.  Both solves go to 1e-11 relative residual: the FP64 floor of the
+    adjoint, whose solution is about 5e4 times larger in |A||lambda| than
+    its right-hand side."""
+    from paper_2512_22215_amd import LduMatrix, ldu_solve
+    gold = _golden("c5")
     c = config_case("c5")
-    ab = c.meta["a_boundary"]
-    xt = c.meta["x_target"]
+    ab = _t(c.meta["a_boundary"])
+    xt = _t(c.meta["x_target"])
     m = LduMatrix.from_case(c)
-    A = O.Ldu.from_case(c)
-    b = c.rhs[0]
-    # 1e-11: the FP64 residual floor of the adjoint right-hand side x - x_t
-    # is about 2e-12 on this system (the oracle stalls there)
-    x, st = m.pcg(_t(b), rel_tol=1e-11, max_iter=5000)
-    xn = x.cpu().numpy()
-    assert st.converged and _res(A, b, xn) <= 1e-11
-    g = xn - xt
-    lam, sa = m.adjoint(_t(g), rel_tol=1e-11, max_iter=5000)
-    lg = lam.cpu().numpy()
-    ref = O.pcg(A, g, tol=1e-11, max_iter=5000, transpose=True)
-    assert sa.converged and ref.status == O.OK
-    # two solutions at 1e-11 residual differ by at most about kappa * 1e-11
-    assert np.linalg.norm(lg - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
-    gd, gu, gl = (t.cpu().numpy() for t in m.coeff_grad(lam, x))
-    rd, ru, rl = O.coeff_grad(A, ref.x, xn)
-    for got, want in ((gd, rd), (gu, ru), (gl, rl)):
-        assert np.linalg.norm(got - want) <= 1e-7 * np.linalg.norm(want)
-    # symmetric face coefficient gradient, central differences on 20 faces at
-    # relative step 1e-6.  The difference L(a+h) - L(a-h) is evaluated in
-    # increment form: x(a+-h) = x + d+- with A+- d+- = b - A+- x, so
-    # L+ - L- = (x - x_t).(d+ - d-) + (|d+|^2 - |d-|^2)/2 exactly, and the
-    # O(1e6) losses never cancel against each other.
-    gc = gu + gl - gd[c.owner] - gd[c.neighbour]
-    bt = _t(b)
-    dx = xn - xt
+    m.gamg_setup(n_pre=1, n_post=1)
+    own = torch.from_numpy(c.owner.astype(np.int64)).cuda()
+    nb = torch.from_numpy(c.neighbour.astype(np.int64)).cuda()
+    zero = torch.zeros(c.n_cells, dtype=torch.float64, device="cuda")
 
-    def increment(a):
-        d = assemble_diag(c.n_cells, c.owner, c.neighbour, a, a, ab)
-        m.set_coeffs(_t(d), _t(a), _t(a))
-        r = bt - m.amul(x)
-        inc, s = m.pcg(r, rel_tol=1e-11, max_iter=20000)
-        assert s.converged
-        return inc.cpu().numpy()
+    def assemble(a):
+        return -(zero.index_add(0, own, a).index_add(0, nb, a)) - ab
 
-    # per face: 1e-5 relative, plus an absolute floor for faces whose gradient
-    # is orders of magnitude below the largest: x and lambda carry errors of
-    # about kappa * 1e-11 (kappa ~ 1e5 here), and each face gradient is a
-    # product of differences of them, so faces near max|g| * 1e-4 see that
-    # error at the 1e-7 * max|g| level
-    gmax = np.abs(gc).max()
-    for f in c.meta["fd_faces"]:
-        h = 1e-6 * c.upper[f]
-        ap = c.upper.copy(); ap[f] += h
-        am = c.upper.copy(); am[f] -= h
-        dp, dm = increment(ap), increment(am)
-        fd = (dx @ (dp - dm) + 0.5 * (dp @ dp - dm @ dm)) / (2 * h)
-        print(f"face {f}: adjoint {gc[f]:.9e} fd {fd:.9e}")
-        assert abs(fd - gc[f]) <= 1e-5 * abs(gc[f]) + 1e-7 * gmax, (f, fd, gc[f])
+    fidx = torch.from_numpy(np.asarray(gold["face_indices"], dtype=np.int64)).cuda()
+    cidx = torch.from_numpy(np.asarray(gold["indices"], dtype=np.int64)).cuda()
+    fd_faces = np.asarray(gold["fd_faces"])
+    fd = np.asarray(gold["fd_central_rel_step_1e-6"])
+    gmax = gold["grad_c_max_abs"]
+    gc_ref = np.asarray(gold["grad_c_sample"])
+    lam_ref = np.asarray(gold["adjoint"]["x"]["sample"])
+    x_ref = np.asarray(gold["forward"]["x"]["sample"])
+    out = {}
+    for prec in ("mixed", "fp64"):
+        a = _t(c.upper).requires_grad_(True)
+        b = _t(c.rhs[0]).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = ldu_solve(assemble(a), a, a, b, m, "pcg", precond=2, precision=prec,
+                      rel_tol=1e-11)
+        loss = 0.5 * torch.sum((x - xt) ** 2)
+        loss.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        gc = a.grad
+        ex = float(np.linalg.norm(x.detach()[cidx].cpu().numpy() - x_ref) / np.linalg.norm(x_ref))
+        el = float(np.linalg.norm(b.grad[cidx].cpu().numpy() - lam_ref) /
+                   np.linalg.norm(lam_ref))
+        eg = float(np.linalg.norm(gc[fidx].cpu().numpy() - gc_ref) / np.linalg.norm(gc_ref))
+        gfd = gc[torch.from_numpy(fd_faces).cuda()].cpu().numpy()
+        rel_fd = np.abs(gfd - fd) / np.abs(fd)
+        print(f"c5 {prec}: forward + backward {dt:.3f} s; vs oracle: x {ex:.2e}, "
+              f"dL/db {el:.2e}, dL/dc (4096 faces) {eg:.2e}")
+        for f, g, v, r in zip(fd_faces, gfd, fd, rel_fd):
+            print(f"  face {f}: gpu {g:.10e} fd {v:.10e} rel {r:.2e} |g|/max|g| "
+                  f"{abs(v) / gmax:.1e}")
+        # Bounds.  x is solved to 1e-11 against the oracle's 1e-13 and lambda
+        # to 1e-11 against the oracle's 1e-11 (kappa ~ 1e5): both within 1e-6.
+        # The oracle's differences are exact-perturbation central differences
+        # (power-of-two step, exact diagonal change, increment form), accurate
+        # to about 1e-8 (their increments are solved to 1e-12); the oracle's
+        # own adjoint gradient agrees with them to 2e-8 or better.  So every
+        # face, small gradients included, is held to 1e-6.
+        assert ex <= 1e-6 and el <= 1e-6 and eg <= 1e-6, (prec, ex, el, eg)
+        assert np.all(rel_fd <= 1e-6), (prec, rel_fd)
+        out[prec] = (dt, gc.detach().clone())
+    dg = float(torch.linalg.norm(out["mixed"][1] - out["fp64"][1]) /
+               torch.linalg.norm(out["fp64"][1]))
+    print(f"c5: |grad_mixed - grad_fp64| / |grad_fp64| = {dg:.2e}; forward + backward "
+          f"mixed {out['mixed'][0]:.3f} s, fp64 {out['fp64'][0]:.3f} s")
     m.close()
 
 

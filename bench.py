@@ -294,12 +294,13 @@ def run_suite(torch, dev, only=None):
         elif name == "c4":
             m.gamg_setup(n_pre=1, n_post=1)
             rec["levels"] = m.n_levels()
+            gold = load_golden("c4")
             for label, kwp in (("pcg_diag", dict(rel_tol=1e-8)),
                                ("pcg_gamg", dict(rel_tol=1e-8, precond=2))):
                 for prec in ("fp64", "mixed"):
                     runs = []
                     xk = torch.zeros(case.n_cells, dtype=torch.float64, device=dev)
-                    for rk in case.rhs:  # back to back, each warm-started from the last
+                    for k, rk in enumerate(case.rhs):  # back to back, each warm-started
                         bk = tens(rk)
                         torch.cuda.synchronize()
                         t1 = time.perf_counter()
@@ -308,8 +309,11 @@ def run_suite(torch, dev, only=None):
                         dt = time.perf_counter() - t1
                         res = m.residual(bk, xk)
                         assert st.converged and res <= 1e-8, (label, prec, st, res)
+                        # error against the oracle's FP64 solve of the same rhs
+                        orec = gold[f"{label}_fp64"][k] if gold else None
                         runs.append({"s": dt, "iterations": st.iterations,
-                                     "refinements": st.refinements, "true_residual": res})
+                                     "refinements": st.refinements, "true_residual": res,
+                                     "vs_fp64_oracle": sampled_error(xk, gold, orec)})
                     rec[f"{label}_{prec}_3rhs"] = runs
         elif name == "c5":
             rec["pcg_diag_fp64"] = solve_rec(m, b, m.pcg, rel_tol=1e-8)
@@ -335,6 +339,8 @@ def run_suite(torch, dev, only=None):
             xt = tens(case.meta["x_target"])
             zero = torch.zeros(case.n_cells, dtype=torch.float64, device=dev)
             grads = {}
+            gold = load_golden("c5")
+            errs = {}
             for prec in ("fp64", "mixed", "fp64", "mixed"):  # the first pair warms up
                 a = tens(case.upper).requires_grad_(True)
                 bb = tens(case.rhs[0]).requires_grad_(True)
@@ -345,11 +351,28 @@ def run_suite(torch, dev, only=None):
                 (0.5 * torch.sum((x - xt) ** 2)).backward()
                 torch.cuda.synchronize()
                 grads[prec] = (time.perf_counter() - t0, a.grad)
+                if gold:  # against the oracle's full-size adjoint run (sampled)
+                    fidx = torch.from_numpy(np.asarray(gold["face_indices"])).to(dev)
+                    cidx = torch.from_numpy(np.asarray(gold["indices"])).to(dev)
+
+                    def rel(got, idx, want):
+                        want = np.asarray(want)
+                        got = got.detach()[idx].cpu().numpy()
+                        return float(np.linalg.norm(got - want) / np.linalg.norm(want))
+                    fd = np.asarray(gold["fd_central_rel_step_1e-6"])
+                    gfd = a.grad[torch.from_numpy(np.asarray(gold["fd_faces"])).to(dev)]
+                    errs[prec] = {
+                        "x": rel(x, cidx, gold["forward"]["x"]["sample"]),
+                        "dL_db": rel(bb.grad, cidx, gold["adjoint"]["x"]["sample"]),
+                        "dL_dc": rel(a.grad, fidx, gold["grad_c_sample"]),
+                        "fd_max_rel": float(np.max(np.abs(gfd.cpu().numpy() - fd) /
+                                                   np.abs(fd)))}
             rec["autograd_forward_backward_1e-11"] = {
                 "fp64_s": grads["fp64"][0], "mixed_s": grads["mixed"][0],
                 "grad_mixed_vs_fp64_rel": float(torch.linalg.norm(grads["mixed"][1] -
                                                                   grads["fp64"][1]) /
-                                                torch.linalg.norm(grads["fp64"][1]))}
+                                                torch.linalg.norm(grads["fp64"][1])),
+                "vs_oracle": errs or None}
             lam = tens(np.zeros(case.n_cells))
             tg = time_kernel(lambda: m.coeff_grad(lam, zero), 20, torch)
             rec["coeff_grad_us"] = tg * 1e6

@@ -8,7 +8,8 @@
  *
  * Arguments are DEVICE pointers (16-byte aligned, as torch allocations are),
  * n counts doubles, blocks is the grid size (<= 0: 2048; at most
- * LDU_STREAM_MAX_BLOCKS), hip_stream a hipStream_t.  The calls only launch:
+ * LDU_STREAM_MAX_BLOCKS), nontemporal != 0 streams with nontemporal loads
+ * and stores (past the caches), hip_stream a hipStream_t.  The calls only launch:
  * time them with events on hip_stream.  Return 0, -1 for a bad argument, -6
  * when the launch failed.  Nothing is allocated.
  */
@@ -25,14 +26,15 @@ extern "C" {
 
 /* read-only: partials[b] = sum of the doubles block b read (8 n bytes) */
 int ldu_stream_read(const double *a, int64_t n, double *partials, int blocks,
-                    void *hip_stream);
+                    int nontemporal, void *hip_stream);
 /* b = a (16 n bytes) */
 int ldu_stream_copy(const double *a, double *b, int64_t n, int blocks,
-                    void *hip_stream);
+                    int nontemporal, void *hip_stream);
 /* x += alpha p; r -= alpha q (48 n bytes: four reads, two writes), the
  * vector update of a CG iteration */
 int ldu_stream_cg_update(double *x, double *r, const double *p, const double *q,
-                         double alpha, int64_t n, int blocks, void *hip_stream);
+                         double alpha, int64_t n, int blocks, int nontemporal,
+                         void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -170,6 +170,20 @@ inline void launch_finalize(double *partials, int nblocks, DevScalars *ds, const
     k_finalize<K, M, Epi><<<1, kBlock, 0, st>>>(partials, nblocks, ds, epi);
 }
 
+// Loads and stores of the level-0 vector streams.  NT: nontemporal, for
+// vectors too large to stay in the 256 MB Infinity Cache between kernels
+// (kStreamNtCells); below that the plain forms keep them there.
+template <bool NT, typename T>
+__device__ __forceinline__ T vld(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void vst(T *p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // row stored at slice position p, and the slice position of row i
 template <bool CMP, typename T>
 __device__ __forceinline__ int32_t sv_row(const SellView<T> &A, int64_t p) {

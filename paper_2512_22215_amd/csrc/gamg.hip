@@ -1833,6 +1833,7 @@ struct EpiRho {
 };
 
 // x += alpha p; r -= alpha q; ||r||^2
+template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_pg_update(int32_t n, int64_t S, double *__restrict__ x, double *__restrict__ r,
             const double *__restrict__ p, const double *__restrict__ q, double *partials,
@@ -1844,9 +1845,9 @@ k_pg_update(int32_t n, int64_t S, double *__restrict__ x, double *__restrict__ r
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
         if (i < n) {
-            x[i] = x[i] + alpha * p[i];
-            const double ri = r[i] - alpha * q[i];
-            r[i] = ri;
+            vst<NT>(x + i, vld<NT>(x + i) + alpha * vld<NT>(p + i));
+            const double ri = vld<NT>(r + i) - alpha * vld<NT>(q + i);
+            vst<NT>(r + i, ri);
             acc[0] += ri * ri;
         }
     });
@@ -1876,6 +1877,7 @@ struct EpiBeta {
 };
 
 // p = z + beta p
+template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_pg_p(int32_t n, int64_t S, const double *__restrict__ z, double *__restrict__ p,
        const DevScalars *ds) {
@@ -1884,7 +1886,7 @@ k_pg_p(int32_t n, int64_t S, const double *__restrict__ z, double *__restrict__ 
     const int lane = threadIdx.x & 63;
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
-        if (i < n) p[i] = z[i] + beta * p[i];
+        if (i < n) vst<NT>(p + i, vld<NT>(z + i) + beta * vld<NT>(p + i));
     });
 }
 
@@ -1897,6 +1899,7 @@ int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, b
     const int n = L.n;
     const int64_t S = L.A.nslices;
     const int G = stream_grid_slices(S);
+    const bool nt = n > kStreamNtCells;
     ensure_hist(h, (int64_t)o.max_iter + 2);
     fill_level_stats(h, stats);
     if (stats) { stats->refinements = 0; stats->history_count = 0; }
@@ -1927,14 +1930,19 @@ int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, b
         for (;;) {
             for (int k = 0; k < every; ++k) {
                 launch_pcg_q(h, A, h->p, h->q, G, st);
-                k_pg_update<<<G, kBlock, 0, st>>>(n, S, x, h->r, h->p, h->q, h->partials,
-                                                  h->dev);
+                if (nt)
+                    k_pg_update<true><<<G, kBlock, 0, st>>>(n, S, x, h->r, h->p, h->q,
+                                                            h->partials, h->dev);
+                else
+                    k_pg_update<false><<<G, kBlock, 0, st>>>(n, S, x, h->r, h->p, h->q,
+                                                             h->partials, h->dev);
                 launch_converge(h, G, false, st);
                 bool dotted = false;
                 z = vcycle<double>(c, 0, h->r, h->r, &dotted);
                 if (!dotted) k_pg_rz<<<G, kBlock, 0, st>>>(n, S, h->r, z, h->partials, h->dev);
                 launch_finalize<1>(h->partials, G, h->dev, EpiBeta{}, st);
-                k_pg_p<<<G, kBlock, 0, st>>>(n, S, z, h->p, h->dev);
+                if (nt) k_pg_p<true><<<G, kBlock, 0, st>>>(n, S, z, h->p, h->dev);
+                else k_pg_p<false><<<G, kBlock, 0, st>>>(n, S, z, h->p, h->dev);
             }
             HIP_CHECK(hipGetLastError());
             read_scalars(h, st);

@@ -54,6 +54,10 @@ constexpr int kPlainF64ProductBlocks = 1024;
 #define LDU_CMP_BATCH 24
 #endif
 constexpr int kCmpBatch = LDU_CMP_BATCH;  // compressed-slice row products: entries per batch
+// level-0 vector kernels stream their vectors with nontemporal loads and
+// stores above this many cells: four FP64 vectors then exceed the 256 MB
+// Infinity Cache, which below it keeps them between kernels
+constexpr int64_t kStreamNtCells = 12000000;
 constexpr int kMaxLevels = 64;
 constexpr int kMaxCoarseRow = 128; // widest coarse-level row the setup supports
 constexpr double kCoarsestTol = 1e-10;

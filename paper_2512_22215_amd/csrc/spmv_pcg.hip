@@ -245,6 +245,7 @@ void launch_pcg_q(ldu_t *h, const SellView<double> &A, const double *p, double *
 }
 
 // x += alpha p; r -= alpha q; ||r||^2 and r.D^-1 r
+template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restrict__ x,
              double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ q,
@@ -256,11 +257,11 @@ k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restr
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
         if (i < n) {
-            const double xi = x[i] + alpha * p[i];
-            const double ri = r[i] - alpha * q[i];
-            x[i] = xi;
-            r[i] = ri;
-            const double zi = precond ? ri / D[i] : ri;
+            const double xi = vld<NT>(x + i) + alpha * vld<NT>(p + i);
+            const double ri = vld<NT>(r + i) - alpha * vld<NT>(q + i);
+            vst<NT>(x + i, xi);
+            vst<NT>(r + i, ri);
+            const double zi = precond ? ri / vld<NT>(D + i) : ri;
             acc[0] += ri * ri;
             acc[1] += ri * zi;
         }
@@ -302,6 +303,7 @@ void launch_converge(ldu_t *h, int grid, bool with_beta, hipStream_t st) {
 }
 
 // p = D^-1 r + beta p
+template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_pcg_p(int32_t n, int64_t S, const double *__restrict__ D, const double *__restrict__ r,
         double *__restrict__ p, int precond, const DevScalars *ds) {
@@ -311,8 +313,9 @@ k_pcg_p(int32_t n, int64_t S, const double *__restrict__ D, const double *__rest
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
         if (i < n) {
-            const double zi = precond ? r[i] / D[i] : r[i];
-            p[i] = zi + beta * p[i];
+            const double ri = vld<NT>(r + i);
+            const double zi = precond ? ri / vld<NT>(D + i) : ri;
+            vst<NT>(p + i, zi + beta * vld<NT>(p + i));
         }
     });
 }
@@ -347,6 +350,7 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
     const int64_t S = L.A.nslices;
     const int G = stream_grid_slices(S);
     const int precond = o.precond ? 1 : 0;
+    const bool nt = n > kStreamNtCells;
     ensure_hist(h, (int64_t)o.max_iter + 2);
     fill_stats_common(stats);
     set_scalars_for_solve(h, o.rel_tol, o.max_iter, st);
@@ -373,10 +377,15 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
         for (;;) {
             for (int k = 0; k < every; ++k) {
                 launch_pcg_q(h, A, h->p, h->q, G, st);
-                k_pcg_update<<<G, kBlock, 0, st>>>(n, S, A.diag, x, h->r, h->p, h->q, precond,
-                                                   h->partials, h->dev);
+                if (nt)
+                    k_pcg_update<true><<<G, kBlock, 0, st>>>(n, S, A.diag, x, h->r, h->p, h->q,
+                                                             precond, h->partials, h->dev);
+                else
+                    k_pcg_update<false><<<G, kBlock, 0, st>>>(n, S, A.diag, x, h->r, h->p, h->q,
+                                                              precond, h->partials, h->dev);
                 launch_converge(h, G, true, st);
-                k_pcg_p<<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->p, precond, h->dev);
+                if (nt) k_pcg_p<true><<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->p, precond, h->dev);
+                else k_pcg_p<false><<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->p, precond, h->dev);
             }
             HIP_CHECK(hipGetLastError());
             read_scalars(h, st);

@@ -5,9 +5,15 @@
 // kernel can draw from HBM on this device; the solver kernels are compared
 // with it as well as with the vendor peak.
 //
-// Each thread moves 16 bytes per load (double2) and keeps UNROLL loads in
-// flight over a grid-stride loop; tails shorter than a double2 are handled
-// by the first thread.  Nothing is allocated: the read kernel writes one
+// Shape (the fastest of a sweep over grid-stride and chunked loops, 4-16
+// loads in flight per thread, plain and nontemporal accesses, on MI355X):
+// each block walks chunks of U x 256 16-byte elements, chunk c, c + grid,
+// ...; thread t of the block loads elements t, t + 256, ... of the chunk, so
+// one wave's loads cover contiguous 1 KiB runs and a thread keeps U loads in
+// flight.  NT selects nontemporal loads and stores, which stream past the
+// caches: faster for arrays well above the 256 MB Infinity Cache, slower for
+// arrays that fit it.  Tails shorter than a 16-byte element are handled by
+// the first thread.  Nothing is allocated: the read kernel writes one
 // partial per block into the caller's array.
 #include <hip/hip_runtime.h>
 
@@ -18,34 +24,64 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kUnroll = 4;
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ __forceinline__ v2d ld2(const v2d *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st2(v2d *p, v2d v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 int grid_of(int blocks) {
     if (blocks <= 0) return 2048;
     return blocks > LDU_STREAM_MAX_BLOCKS ? LDU_STREAM_MAX_BLOCKS : blocks;
 }
 
-__global__ void __launch_bounds__(kThreads) k_read(const double2 *__restrict__ a, int64_t n2,
-                                                   const double *__restrict__ tail, int ntail,
-                                                   double *out) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    double s0 = 0.0, s1 = 0.0;
-    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    for (; i + (kUnroll - 1) * stride < n2; i += kUnroll * stride) {
-        double2 v[kUnroll];
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) v[k] = a[i + k * stride];
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-            s0 += v[k].x;
-            s1 += v[k].y;
+// chunks of U * kThreads elements; f(element index, u) for each of a
+// thread's U elements of a full chunk, g(element index) for a partial one
+template <int U, class F, class G>
+__device__ __forceinline__ void for_each_chunk(int64_t n2, F &&f, G &&g) {
+    const int64_t ch = (int64_t)U * kThreads;
+    for (int64_t c = blockIdx.x; c * ch < n2; c += gridDim.x) {
+        const int64_t b = c * ch + threadIdx.x;
+        if (b + (int64_t)(U - 1) * kThreads < n2) {
+            f(b);
+        } else {
+            for (int u = 0; u < U; ++u)
+                if (b + (int64_t)u * kThreads < n2) g(b + (int64_t)u * kThreads);
         }
     }
-    for (; i < n2; i += stride) {
-        const double2 v = a[i];
-        s0 += v.x;
-        s1 += v.y;
-    }
+}
+
+template <bool NT>
+__global__ void __launch_bounds__(kThreads) k_read(const v2d *__restrict__ a, int64_t n2,
+                                                   const double *__restrict__ tail, int ntail,
+                                                   double *out) {
+    constexpr int U = 8;
+    double s0 = 0.0, s1 = 0.0;
+    for_each_chunk<U>(
+        n2,
+        [&](int64_t b) {
+            v2d v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = ld2<NT>(a + b + u * kThreads);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                s0 += v[u].x;
+                s1 += v[u].y;
+            }
+        },
+        [&](int64_t j) {
+            const v2d v = a[j];
+            s0 += v.x;
+            s1 += v.y;
+        });
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (int k = 0; k < ntail; ++k) s0 += tail[k];
     __shared__ double sm[kThreads];
@@ -58,61 +94,55 @@ __global__ void __launch_bounds__(kThreads) k_read(const double2 *__restrict__ a
     if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
 }
 
-__global__ void __launch_bounds__(kThreads) k_copy(const double2 *__restrict__ a,
-                                                   double2 *__restrict__ b, int64_t n2,
-                                                   const double *__restrict__ ta,
+template <bool NT>
+__global__ void __launch_bounds__(kThreads) k_copy(const v2d *__restrict__ a, v2d *__restrict__ b,
+                                                   int64_t n2, const double *__restrict__ ta,
                                                    double *__restrict__ tb, int ntail) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    for (; i + (kUnroll - 1) * stride < n2; i += kUnroll * stride) {
-        double2 v[kUnroll];
+    constexpr int U = 8;
+    for_each_chunk<U>(
+        n2,
+        [&](int64_t j) {
+            v2d v[U];
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) v[k] = a[i + k * stride];
+            for (int u = 0; u < U; ++u) v[u] = ld2<NT>(a + j + u * kThreads);
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) b[i + k * stride] = v[k];
-    }
-    for (; i < n2; i += stride) b[i] = a[i];
+            for (int u = 0; u < U; ++u) st2<NT>(b + j + u * kThreads, v[u]);
+        },
+        [&](int64_t j) { b[j] = a[j]; });
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (int k = 0; k < ntail; ++k) tb[k] = ta[k];
 }
 
-__device__ __forceinline__ void cg_step(double2 &x, double2 &r, const double2 p,
-                                        const double2 q, double alpha) {
-    x.x = x.x + alpha * p.x;
-    x.y = x.y + alpha * p.y;
-    r.x = r.x - alpha * q.x;
-    r.y = r.y - alpha * q.y;
-}
-
+template <bool NT>
 __global__ void __launch_bounds__(kThreads)
-k_cg_update(double2 *__restrict__ x, double2 *__restrict__ r, const double2 *__restrict__ p,
-            const double2 *__restrict__ q, double alpha, int64_t n2, double *__restrict__ tx,
+k_cg_update(v2d *__restrict__ x, v2d *__restrict__ r, const v2d *__restrict__ p,
+            const v2d *__restrict__ q, double alpha, int64_t n2, double *__restrict__ tx,
             double *__restrict__ tr, const double *__restrict__ tp,
             const double *__restrict__ tq, int ntail) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    for (; i + stride < n2; i += 2 * stride) {
-        double2 xv[2], rv[2], pv[2], qv[2];
+    constexpr int U = 2;
+    for_each_chunk<U>(
+        n2,
+        [&](int64_t b) {
+            v2d xv[U], rv[U], pv[U], qv[U];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            xv[k] = x[i + k * stride];
-            rv[k] = r[i + k * stride];
-            pv[k] = p[i + k * stride];
-            qv[k] = q[i + k * stride];
-        }
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = b + u * kThreads;
+                xv[u] = ld2<NT>(x + j);
+                rv[u] = ld2<NT>(r + j);
+                pv[u] = ld2<NT>(p + j);
+                qv[u] = ld2<NT>(q + j);
+            }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            cg_step(xv[k], rv[k], pv[k], qv[k], alpha);
-            x[i + k * stride] = xv[k];
-            r[i + k * stride] = rv[k];
-        }
-    }
-    for (; i < n2; i += stride) {
-        double2 xv = x[i], rv = r[i];
-        cg_step(xv, rv, p[i], q[i], alpha);
-        x[i] = xv;
-        r[i] = rv;
-    }
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = b + u * kThreads;
+                st2<NT>(x + j, xv[u] + alpha * pv[u]);
+                st2<NT>(r + j, rv[u] - alpha * qv[u]);
+            }
+        },
+        [&](int64_t j) {
+            x[j] = x[j] + alpha * p[j];
+            r[j] = r[j] - alpha * q[j];
+        });
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (int k = 0; k < ntail; ++k) {
             tx[k] = tx[k] + alpha * tp[k];
@@ -124,41 +154,59 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 
 
 int launched() { return hipGetLastError() == hipSuccess ? 0 : -6; }
 
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
 }  // namespace
 
 extern "C" {
 
-int ldu_stream_read(const double *a, int64_t n, double *partials, int blocks,
+int ldu_stream_read(const double *a, int64_t n, double *partials, int blocks, int nontemporal,
                     void *hip_stream) {
     if (!a || !partials || n < 0 || !aligned16(a)) return -1;
     const int G = grid_of(blocks);
     const int64_t n2 = n / 2;
-    k_read<<<G, kThreads, 0, reinterpret_cast<hipStream_t>(hip_stream)>>>(
-        reinterpret_cast<const double2 *>(a), n2, a + 2 * n2, (int)(n - 2 * n2), partials);
+    const v2d *a2 = reinterpret_cast<const v2d *>(a);
+    if (nontemporal)
+        k_read<true><<<G, kThreads, 0, S(hip_stream)>>>(a2, n2, a + 2 * n2, (int)(n - 2 * n2),
+                                                        partials);
+    else
+        k_read<false><<<G, kThreads, 0, S(hip_stream)>>>(a2, n2, a + 2 * n2, (int)(n - 2 * n2),
+                                                         partials);
     return launched();
 }
 
-int ldu_stream_copy(const double *a, double *b, int64_t n, int blocks, void *hip_stream) {
+int ldu_stream_copy(const double *a, double *b, int64_t n, int blocks, int nontemporal,
+                    void *hip_stream) {
     if (!a || !b || n < 0 || !aligned16(a) || !aligned16(b)) return -1;
     const int G = grid_of(blocks);
     const int64_t n2 = n / 2;
-    k_copy<<<G, kThreads, 0, reinterpret_cast<hipStream_t>(hip_stream)>>>(
-        reinterpret_cast<const double2 *>(a), reinterpret_cast<double2 *>(b), n2, a + 2 * n2,
-        b + 2 * n2, (int)(n - 2 * n2));
+    const v2d *a2 = reinterpret_cast<const v2d *>(a);
+    v2d *b2 = reinterpret_cast<v2d *>(b);
+    if (nontemporal)
+        k_copy<true><<<G, kThreads, 0, S(hip_stream)>>>(a2, b2, n2, a + 2 * n2, b + 2 * n2,
+                                                        (int)(n - 2 * n2));
+    else
+        k_copy<false><<<G, kThreads, 0, S(hip_stream)>>>(a2, b2, n2, a + 2 * n2, b + 2 * n2,
+                                                         (int)(n - 2 * n2));
     return launched();
 }
 
 int ldu_stream_cg_update(double *x, double *r, const double *p, const double *q, double alpha,
-                         int64_t n, int blocks, void *hip_stream) {
+                         int64_t n, int blocks, int nontemporal, void *hip_stream) {
     if (!x || !r || !p || !q || n < 0 || !aligned16(x) || !aligned16(r) || !aligned16(p) ||
         !aligned16(q))
         return -1;
     const int G = grid_of(blocks);
     const int64_t n2 = n / 2;
-    k_cg_update<<<G, kThreads, 0, reinterpret_cast<hipStream_t>(hip_stream)>>>(
-        reinterpret_cast<double2 *>(x), reinterpret_cast<double2 *>(r),
-        reinterpret_cast<const double2 *>(p), reinterpret_cast<const double2 *>(q), alpha, n2,
-        x + 2 * n2, r + 2 * n2, p + 2 * n2, q + 2 * n2, (int)(n - 2 * n2));
+    v2d *x2 = reinterpret_cast<v2d *>(x), *r2 = reinterpret_cast<v2d *>(r);
+    const v2d *p2 = reinterpret_cast<const v2d *>(p), *q2 = reinterpret_cast<const v2d *>(q);
+    const int nt = (int)(n - 2 * n2);
+    if (nontemporal)
+        k_cg_update<true><<<G, kThreads, 0, S(hip_stream)>>>(x2, r2, p2, q2, alpha, n2, x + 2 * n2,
+                                                             r + 2 * n2, p + 2 * n2, q + 2 * n2, nt);
+    else
+        k_cg_update<false><<<G, kThreads, 0, S(hip_stream)>>>(
+            x2, r2, p2, q2, alpha, n2, x + 2 * n2, r + 2 * n2, p + 2 * n2, q + 2 * n2, nt);
     return launched();
 }
 

@@ -112,9 +112,9 @@ def lib():
     L.ldu_assemble_pressure.argtypes = [vp] * 13
     L.ldu_last_error.restype = C.c_char_p
     # bandwidth-ceiling kernels of ldu_bench.h
-    L.ldu_stream_read.argtypes = [vp, i64, vp, i, vp]
-    L.ldu_stream_copy.argtypes = [vp, vp, i64, i, vp]
-    L.ldu_stream_cg_update.argtypes = [vp, vp, vp, vp, C.c_double, i64, i, vp]
+    L.ldu_stream_read.argtypes = [vp, i64, vp, i, i, vp]
+    L.ldu_stream_copy.argtypes = [vp, vp, i64, i, i, vp]
+    L.ldu_stream_cg_update.argtypes = [vp, vp, vp, vp, C.c_double, i64, i, i, vp]
     for name in BENCH_EXPORTED:
         getattr(L, name).restype = C.c_int
     for name in EXPORTED:

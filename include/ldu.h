@@ -186,6 +186,20 @@ int ldu_residual(ldu_handle h, const double *b, const double *x, double *out,
 int pcg_solve(ldu_handle h, const double *b, double *x,
               const ldu_pcg_opts *opts, ldu_stats *stats, void *hip_stream);
 
+/* pcg_solve without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as pcg_solve with
+ * precond 0 or 1 and precision LDU_FP64 (anything else: LDU_ERR_ARG).  The
+ * CG vectors, reduction partials and residual history live in a static
+ * device array of the library (24.1 MiB per GPU, held until the process
+ * ends), not in the handle: nCells must be at most 1,048,576 (else
+ * LDU_ERR_LIMIT) and at most the first 4096 history entries are kept.
+ * Every call on one GPU shares that array, so calls that overlap on a GPU
+ * (other streams or threads) race.  The handle itself is created by
+ * ldu_create, which allocates. */
+int pcg_solve_noalloc(ldu_handle h, const double *b, double *x,
+                      const ldu_pcg_opts *opts, ldu_stats *stats, void *hip_stream);
+
 /* PBiCG for non-symmetric A (the paper's solver for the velocity and
  * turbulence systems, Appendix A): preconditioned bi-conjugate gradients with
  * the shadow residual equal to the residual at each (re)start, one fused

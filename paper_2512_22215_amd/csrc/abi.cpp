@@ -168,6 +168,7 @@ int ldu_create(int32_t nCells, int64_t nFaces, const int32_t *owner, const int32
     int rc = guarded(nullptr, [&] {
         hipStream_t st = S(hip_stream);
         HIP_CHECK(hipGetDevice(&h->device));
+        noalloc_init(h->device);  // the static scratch's address on this device
         Level &L = h->L0;
         L.n = nCells;
         L.nf = nFaces;
@@ -336,6 +337,21 @@ static int pcg_common(ldu_handle h, const double *b, double *x, const ldu_pcg_op
 int pcg_solve(ldu_handle h, const double *b, double *x, const ldu_pcg_opts *opts,
               ldu_stats *stats, void *hip_stream) {
     return pcg_common(h, b, x, opts, stats, hip_stream, false);
+}
+
+int pcg_solve_noalloc(ldu_handle h, const double *b, double *x, const ldu_pcg_opts *opts,
+                      ldu_stats *stats, void *hip_stream) {
+    if (!h || !b || !x) return fail(LDU_ERR_ARG, "NULL argument");
+    return guarded(h, [&] {
+        ldu_pcg_opts o;
+        ldu_pcg_default_opts(&o);
+        if (opts) o = *opts;
+        check_pcg_opts(o);
+        if (o.precond == 2 || o.precision != LDU_FP64)
+            throw Error(LDU_ERR_ARG,
+                        "pcg_solve_noalloc: precond 0 or 1 and precision LDU_FP64 only");
+        return pcg_fp64_noalloc(h, b, x, o, stats, S(hip_stream));
+    });
 }
 
 int gamg_setup(ldu_handle h, const ldu_gamg_opts *opts, void *hip_stream) {

@@ -263,12 +263,18 @@ void set_scalars_for_solve(ldu_t *h, double tol, int max_iter, hipStream_t st);
 double residual_norm(ldu_t *h, const Level &L, bool tr, const double *b,
                      const double *x, double *r_out, hipStream_t st);
 int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o,
-             bool tr, ldu_stats *stats, hipStream_t st);
+             bool tr, ldu_stats *stats, hipStream_t st, bool own_hist = true);
 int pbicg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
                ldu_stats *stats, hipStream_t st);
 int pcg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o,
               bool tr, ldu_stats *stats, hipStream_t st);
 void ensure_hist(ldu_t *h, int64_t entries);
+// noalloc.hip: the allocation-free diagonal-PCG entry point's static scratch
+constexpr int64_t kNoAllocMaxCells = int64_t(1) << 20;
+constexpr int kNoAllocHistory = 4096;
+void noalloc_init(int device);
+int pcg_fp64_noalloc(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o,
+                     ldu_stats *stats, hipStream_t st);
 void copy_history(ldu_t *h, ldu_stats *stats, int count, hipStream_t st);
 void launch_coeff_grad(const Level &L, const double *lam, const double *x,
                        double *gd, double *gu, double *gl, hipStream_t st);

@@ -343,7 +343,7 @@ static void fill_stats_common(ldu_stats *stats) {
 }
 
 int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool tr,
-             ldu_stats *stats, hipStream_t st) {
+             ldu_stats *stats, hipStream_t st, bool own_hist) {
     const Level &L = h->L0;
     const SellView<double> A = L.A.view(tr);
     const int n = L.n;
@@ -351,7 +351,7 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
     const int G = stream_grid_slices(S);
     const int precond = o.precond ? 1 : 0;
     const bool nt = n > kStreamNtCells;
-    ensure_hist(h, (int64_t)o.max_iter + 2);
+    if (own_hist) ensure_hist(h, (int64_t)o.max_iter + 2);
     fill_stats_common(stats);
     set_scalars_for_solve(h, o.rel_tol, o.max_iter, st);
     launch_residual<true, false>(h, A, b, x, h->r, h->p, precond, kResPlain, true, st);

@@ -24,6 +24,7 @@ SOLVERS = {"pcg": 0, "gamg": 1, "pbicg": 2}
 EXPORTED = (
     "ldu_pcg_default_opts", "ldu_gamg_default_opts", "ldu_create", "ldu_set_coeffs",
     "ldu_destroy", "ldu_amul", "ldu_tmul", "ldu_amul_f32", "ldu_residual", "pcg_solve",
+    "pcg_solve_noalloc",
     "pbicg_solve", "gamg_setup", "gamg_solve", "gamg_vcycle", "gamg_level_size", "gamg_level_export",
     "ldu_level_layout", "ldu_adjoint_solve", "ldu_coeff_grad", "ldu_assemble_pressure", "ldu_last_error",
 )
@@ -101,6 +102,7 @@ def lib():
     L.ldu_residual.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
     L.pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(Stats), vp]
     L.pbicg_solve.argtypes = L.pcg_solve.argtypes
+    L.pcg_solve_noalloc.argtypes = L.pcg_solve.argtypes
     L.gamg_setup.argtypes = [vp, C.POINTER(GamgOpts), vp]
     L.gamg_solve.argtypes = [vp, vp, vp, C.POINTER(GamgOpts), C.POINTER(Stats), vp]
     L.gamg_vcycle.argtypes = [vp, vp, vp, C.POINTER(GamgOpts), vp]
@@ -272,6 +274,11 @@ class LduMatrix:
 
     def pcg(self, b, x0=None, history=0, **kw):
         return self._solve(lib().pcg_solve, b, x0, pcg_opts(**kw), history)
+
+    def pcg_noalloc(self, b, x0=None, history=0, **kw):
+        """pcg_solve_noalloc: diagonal (or no) preconditioner, FP64, with the
+        library's static scratch instead of device allocations."""
+        return self._solve(lib().pcg_solve_noalloc, b, x0, pcg_opts(**kw), history)
 
     def gamg(self, b, x0=None, history=0, **kw):
         return self._solve(lib().gamg_solve, b, x0, gamg_opts(**kw), history)

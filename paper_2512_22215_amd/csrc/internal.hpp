@@ -49,7 +49,10 @@ constexpr int kMaxGrid = 2048;     // streaming kernels: at most this many block
 // rest only contribute zero partials).  Four waves per SIMD instead of eight
 // keep fewer of the streamed matrix lines in flight, so more of x survives
 // in L2 between its reuses one mesh plane apart.
-constexpr int kPlainF64ProductBlocks = 1024;
+#ifndef LDU_PLAIN_F64_BLOCKS
+#define LDU_PLAIN_F64_BLOCKS 1024
+#endif
+constexpr int kPlainF64ProductBlocks = LDU_PLAIN_F64_BLOCKS;
 #ifndef LDU_CMP_BATCH
 #define LDU_CMP_BATCH 24
 #endif
@@ -57,7 +60,10 @@ constexpr int kCmpBatch = LDU_CMP_BATCH;  // compressed-slice row products: entr
 // level-0 vector kernels stream their vectors with nontemporal loads and
 // stores above this many cells: four FP64 vectors then exceed the 256 MB
 // Infinity Cache, which below it keeps them between kernels
-constexpr int64_t kStreamNtCells = 12000000;
+#ifndef LDU_STREAM_NT_CELLS
+#define LDU_STREAM_NT_CELLS 12000000
+#endif
+constexpr int64_t kStreamNtCells = LDU_STREAM_NT_CELLS;
 constexpr int kMaxLevels = 64;
 constexpr int kMaxCoarseRow = 128; // widest coarse-level row the setup supports
 constexpr double kCoarsestTol = 1e-10;

@@ -19,7 +19,8 @@
 namespace ldu {
 
 // ---------------------------------------------------------------- products
-template <bool CMP, typename T>
+// NT: the result is stored nontemporally (level 0 above kStreamNtCells)
+template <bool CMP, typename T, bool NT = false>
 __global__ void __launch_bounds__(kBlock) k_amul(SellView<T> A, const T *__restrict__ x,
                                                  T *__restrict__ y) {
     const int lane = threadIdx.x & 63;
@@ -27,7 +28,7 @@ __global__ void __launch_bounds__(kBlock) k_amul(SellView<T> A, const T *__restr
         const int64_t p = s * kWave + lane;
         if (p < A.n) {
             const int32_t i = sv_row<CMP>(A, p);
-            y[i] = sell_row<CMP>(A, s, lane, i, Direct<T>{x});
+            vst<NT>(y + i, sell_row<CMP>(A, s, lane, i, Direct<T>{x}));
         }
     });
 }
@@ -35,6 +36,7 @@ __global__ void __launch_bounds__(kBlock) k_amul(SellView<T> A, const T *__restr
 void launch_amul(const SellView<double> &A, const double *x, double *y, hipStream_t st) {
     const int G = stream_grid_slices(A.nslices);
     if (A.pdeg) k_amul<true, double><<<G, kBlock, 0, st>>>(A, x, y);
+    else if (A.n > kStreamNtCells) k_amul<false, double, true><<<G, kBlock, 0, st>>>(A, x, y);
     else k_amul<false, double><<<G, kBlock, 0, st>>>(A, x, y);
     HIP_CHECK(hipGetLastError());
 }
@@ -204,7 +206,7 @@ double residual_norm(ldu_t *h, const Level &L, bool tr, const double *b, const d
 
 // ---------------------------------------------------------------- PCG, FP64
 // q = A p and p.q -> alpha = rho / p.q
-template <bool CMP>
+template <bool CMP, bool NT = false>
 __global__ void __launch_bounds__(kBlock)
 k_pcg_q(SellView<double> A, const double *__restrict__ p, double *__restrict__ q,
         double *partials, const DevScalars *ds) {
@@ -216,7 +218,7 @@ k_pcg_q(SellView<double> A, const double *__restrict__ p, double *__restrict__ q
         if (pos < A.n) {
             const int32_t i = sv_row<CMP>(A, pos);
             const double qi = sell_row<CMP>(A, s, lane, i, Direct<double>{p});
-            q[i] = qi;
+            vst<NT>(q + i, qi);
             acc[0] += p[i] * qi;
         }
     });
@@ -240,6 +242,8 @@ struct EpiAlpha {
 void launch_pcg_q(ldu_t *h, const SellView<double> &A, const double *p, double *q, int grid,
                   hipStream_t st) {
     if (A.pdeg) k_pcg_q<true><<<grid, kBlock, 0, st>>>(A, p, q, h->partials, h->dev);
+    else if (A.n > kStreamNtCells)
+        k_pcg_q<false, true><<<grid, kBlock, 0, st>>>(A, p, q, h->partials, h->dev);
     else k_pcg_q<false><<<grid, kBlock, 0, st>>>(A, p, q, h->partials, h->dev);
     launch_finalize<1>(h->partials, grid, h->dev, EpiAlpha{}, st);
 }

@@ -120,6 +120,49 @@ def test_c3_pressure_solve_fp64_and_mixed(c3):
     m.close()
 
 
+def test_c3_aggressive_hierarchy_fp64_and_mixed(c3):
+    """The headline solve on the aggressive hierarchy (pairwise matching from
+    level 0 to 1, three matching passes per level below): level 1's and 2's
+    aggregation and level 2's Galerkin matrix integer- and bit-exact against
+    the oracle's, then the FP64 solve against the oracle's full-size solve on
+    the same hierarchy, and the mixed form against it."""
+    from paper_2512_22215_amd import LduMatrix
+    gold = _golden("c3")
+    rec = gold.get("pcg_gamg_fp64_aggressive")
+    if rec is None:
+        pytest.skip("no aggressive-hierarchy record in fullsize_c3.json")
+    kw = gold["aggressive_settings"]
+    m = LduMatrix.from_case(c3)
+    m.gamg_setup(n_pre=1, n_post=1, **kw)
+    assert [m.level(k)["n"] for k in range(m.n_levels())] == gold["levels_aggressive"]
+    A = O.Ldu.from_case(c3)
+    g = O.Gamg(A, max_levels=3, **kw)
+    for k in (0, 1):
+        assert np.array_equal(m.level(k)["agg"].cpu().numpy(), g.level(k).agg), k
+    l2, r2 = m.level(2), g.level(2)
+    for key, rv in (("owner", r2.owner), ("neighbour", r2.neighbour), ("diag", r2.diag),
+                    ("upper", r2.upper), ("lower", r2.lower)):
+        assert np.array_equal(l2[key].cpu().numpy(), rv), key
+    del g
+    b = c3.rhs[0]
+    x64, s64 = m.pcg(_t(b), precond=2, rel_tol=1e-8, history=1000)
+    xm, sm = m.pcg(_t(b), precond=2, rel_tol=1e-8, precision="mixed")
+    e64, n64 = _vs_oracle(x64, gold, rec)
+    em, nm = _vs_oracle(xm, gold, rec)
+    hr = _hist_rel(s64.history, rec["history"])
+    print(f"c3 aggressive fp64: {s64.iterations} it (oracle {rec['iterations']}), history max "
+          f"rel diff {hr:.2e}, |x - x_orc|/|x_orc| sampled {e64:.2e}, norm diff {n64:.2e}")
+    print(f"c3 aggressive mixed: {sm.refinements} refinements / {sm.iterations} inner it, "
+          f"|x - x_orc|/|x_orc| sampled {em:.2e}, norm diff {nm:.2e}")
+    assert s64.converged and _res(A, b, x64.cpu().numpy()) <= 1e-8
+    assert sm.converged and _res(A, b, xm.cpu().numpy()) <= 1e-8
+    assert s64.iterations == rec["iterations"]
+    assert len(s64.history) == len(rec["history"]) and hr <= 1e-9
+    assert e64 <= 1e-10 and n64 <= 1e-10
+    assert em <= 1e-6 and nm <= 1e-6
+    m.close()
+
+
 def test_c4_three_rhs_warm_started():
     """Three right-hand sides back to back, each warm-started from the last
     solution: CG + V-cycle and diagonal PCG in FP64 against the oracle's
@@ -147,13 +190,21 @@ def test_c4_three_rhs_warm_started():
                     print(f"c4 {label} fp64 rhs {k}: {st.iterations} it (oracle "
                           f"{rec['iterations']}), history max rel diff {hr:.2e}, |x - x_orc|/"
                           f"|x_orc| sampled {e:.2e}, norm diff {nd:.2e}")
-                    assert abs(st.iterations - rec["iterations"]) <= max(1, rec["iterations"] // 100)
-                    assert e <= 1e-6
+                    # the same path as the oracle: equal counts (also over the
+                    # 2100 diagonal-PCG iterations), histories and solutions at
+                    # the FP64 bars of the small cases (measured: histories
+                    # 6e-11, solutions 1.1e-12 or closer)
+                    assert st.iterations == rec["iterations"]
+                    assert len(st.history) == len(rec["history"]) and hr <= 1e-9
+                    assert e <= 1e-10 and nd <= 1e-10
                 else:
                     print(f"c4 {label} mixed rhs {k}: {st.refinements} refinements / "
                           f"{st.iterations} inner it, |x - x_orc|/|x_orc| sampled {e:.2e}, "
                           f"norm diff {nd:.2e}")
-                    assert e <= 1e-3
+                    # another solution at a true residual below 1e-8 (checked
+                    # above): it differs from the FP64 oracle's by up to
+                    # kappa x 1e-8, measured 5e-8 to 6e-7 on these systems
+                    assert e <= 1e-5
     m.close()
 
 

@@ -27,6 +27,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pressure-solve time to 1e-8 rel. residual at 8M cells; Amul HBM GB/s"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# GAMG hierarchies of the headline solve: pairwise handshake matching on
+# every level (the paper's GAMG default), or pairwise from level 0 to 1 and
+# three matching passes per level below, aggregates of about eight cells
+# (the aggressive coarsening the paper names as the remedy for GAMG's many
+# small levels on GPUs, Sec. 4.4)
+HIERARCHIES = {"pairwise": {}, "aggressive": {"passes": 3, "aggressive_from": 1}}
+AGG_TEXT = {"pairwise": "pairwise agglomeration on every level",
+            "aggressive": "pairwise agglomeration from level 0 to 1, three matching passes "
+                          "per level below"}
 
 
 def measured_traffic():
@@ -89,12 +98,13 @@ def host_cpu():
     return cores, model
 
 
-def cpu_baseline(case, iters_gpu, sweeps, t_gpu, sample_iters=6):
+def cpu_baseline(case, iters_gpu, sweeps, t_gpu, sample_iters=6, hierarchy=None):
     """The serial oracle on the host, on the full workload (the same matrix
     and right-hand side as the GPU step), timed in pieces that keep the run
-    bounded: its Amul (mean of 5 calls), its GAMG build (reported, not
-    counted), and sample_iters iterations of the same V-cycle-preconditioned
-    CG (sweeps + sweeps Jacobi sweeps).  The per-iteration time times the
+    bounded: its Amul (mean of 5 calls), its GAMG build with the same
+    agglomeration settings (reported, not counted), and sample_iters
+    iterations of the same V-cycle-preconditioned CG (sweeps + sweeps Jacobi
+    sweeps).  The per-iteration time times the
     GPU's iteration count estimates one oracle solve; COE (Sec. 4.3,
     coefficient of equivalence) = T_cpu * N_cores / (T_gpu * N_gpus) with
     one core and one GPU."""
@@ -108,7 +118,7 @@ def cpu_baseline(case, iters_gpu, sweeps, t_gpu, sample_iters=6):
         ta.append(time.perf_counter() - t0)
     t_amul = float(np.mean(ta))
     t0 = time.perf_counter()
-    g = O.Gamg(A)
+    g = O.Gamg(A, **(hierarchy or {}))
     t_build = time.perf_counter() - t0
     t0 = time.perf_counter()
     r = g.pcg(case.rhs[0], tol=1e-8, max_iter=sample_iters, n_pre=sweeps, n_post=sweeps)
@@ -123,8 +133,9 @@ def cpu_baseline(case, iters_gpu, sweeps, t_gpu, sample_iters=6):
         "sample": (f"serial C oracle, 1 thread of {model} (host exposes {cores}), measured at "
                    f"{case.n_cells:,} cells on the same matrix and rhs: {r.iterations} CG "
                    f"iterations with one {sweeps}+{sweeps}-sweep V-cycle each at {t_iter:.3f} s "
-                   f"per iteration, times the GPU's {iters_gpu} iterations; GAMG build "
-                   f"{t_build:.1f} s not counted"),
+                   f"per iteration ({g.n_levels} levels, agglomeration {hierarchy or 'pairwise'}), "
+                   f"times the GPU's {iters_gpu} iterations; GAMG build {t_build:.1f} s not "
+                   f"counted"),
         "oracle_amul_s": t_amul,
         "oracle_amul_GBps": amul_bytes(case.n_cells, case.n_faces) / t_amul / 1e9,
         "oracle_gamg_build_s": t_build,
@@ -396,6 +407,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sweeps", type=int, default=1,
                     help="Jacobi sweeps before and after the coarse correction")
+    ap.add_argument("--agglomeration", choices=("aggressive", "pairwise"), default="aggressive",
+                    help="hierarchy of the timed solve: pairwise matching from level 0 to 1 "
+                         "and three matching passes per level below (aggressive), or "
+                         "pairwise matching on every level")
     ap.add_argument("--amul-only", action="store_true",
                     help="only the Amul and copy timings (for counter runs)")
     ap.add_argument("--no-extra", action="store_true",
@@ -440,8 +455,9 @@ def main():
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
     free1 = torch.cuda.mem_get_info(dev)[0]
+    hier = HIERARCHIES[args.agglomeration]
     t0 = time.perf_counter()
-    m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
+    m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, **hier)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     free2 = torch.cuda.mem_get_info(dev)[0]
@@ -489,7 +505,8 @@ def main():
     assert st.converged and res <= 1e-8, (st, res)
     t_step = float(np.mean(times))
     gold = load_golden("c3") if args.n == 200 else None
-    grec = gold["pcg_gamg_fp64"] if gold else None
+    gkey = "pcg_gamg_fp64" + ("_aggressive" if args.agglomeration == "aggressive" else "")
+    grec = gold.get(gkey) if gold else None
     err64 = sampled_error(xs, gold, grec)
     if err64:
         log(f"[bench] FP64 vs oracle: sampled |x - x_orc|/|x_orc| "
@@ -518,9 +535,9 @@ def main():
                      "vs_fp64_oracle": sampled_error(xm, gold, grec)}
 
         # standalone GAMG (x += V(b - A x) per cycle, correction scaling on)
-        # from x0 = 0 with a 400-cycle cap, FP64 and mixed: the configured c3
-        # solver; its convergence factor per cycle is what makes CG + V-cycle
-        # the headline solver on this graded mesh
+        # from x0 = 0 with a 400-cycle cap, FP64 and mixed, on the headline
+        # hierarchy: the configured c3 solver; its convergence factor per cycle
+        # is what makes CG + V-cycle the headline solver on this graded mesh
         gamg_rec = {}
         for label, kw in (("fp64_1+1", dict(n_pre=args.sweeps, n_post=args.sweeps)),
                           ("fp64_2+2", dict(n_pre=2, n_post=2)),
@@ -528,7 +545,7 @@ def main():
                                              precision="mixed", max_refine=400))):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            xg, sg = m.gamg(b, rel_tol=1e-8, max_cycles=400, history=500, **kw)
+            xg, sg = m.gamg(b, rel_tol=1e-8, max_cycles=400, history=500, **hier, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             h = np.asarray(sg.history)
@@ -563,61 +580,64 @@ def main():
                    "coeff_grad_us": t_grad * 1e6,
                    "coeff_grad_GBps": amul_bytes(case.n_cells, case.n_faces) / t_grad / 1e9}
 
-        # variants of the same solve (each one warm-up, then the mean of two):
-        # aggressive agglomeration (two or three matching passes per level, or
-        # three below a pairwise first level), the two-stage Gauss-Seidel
-        # smoother, the DIC coarsest preconditioner
+        def timed_pcg(vo, reps=2):
+            m.pcg(b, **vo)
+            vt = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xv, sv = m.pcg(b, **vo)
+                torch.cuda.synchronize()
+                vt.append(time.perf_counter() - t0)
+            vres = m.residual(b, xv)
+            assert sv.converged and vres <= 1e-8, (vo, sv, vres)
+            return xv, {"s": float(np.mean(vt)), "iterations": sv.iterations,
+                        "refinements": sv.refinements, "true_residual": vres}
+
         variants = {}
-        for name, kw in (("aggressive_2pass", dict(passes=2)),
-                         ("aggressive_3pass", dict(passes=3)),
-                         ("aggressive_3pass_below_level1", dict(passes=3, aggressive_from=1)),
-                         ("gs2_smoother", dict(smoother="gs2")),
+        # the other hierarchy of the headline solve, timed as the headline is
+        # (warm-up, then the mean of `steps` solves), against its oracle run
+        other = "pairwise" if args.agglomeration == "aggressive" else "aggressive"
+        m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, **HIERARCHIES[other])
+        okey = "pcg_gamg_fp64" + ("_aggressive" if other == "aggressive" else "")
+        rec = {"levels": m.n_levels(), "settings": HIERARCHIES[other]}
+        for prec in ("fp64", "mixed"):
+            xv, rec[prec] = timed_pcg(dict(opts, precision=prec), reps=args.steps)
+            orec = gold.get(okey) if gold else None
+            rec[prec]["vs_fp64_oracle"] = sampled_error(xv, gold, orec)
+        variants[other + "_hierarchy"] = rec
+        log(f"[bench] {other} hierarchy: {rec['levels']} levels, fp64 {rec['fp64']['s']:.4f} s "
+            f"({rec['fp64']['iterations']} it), mixed {rec['mixed']['s']:.4f} s")
+
+        # agglomeration settings: pairwise matching down to level `from`, then
+        # 2 or 3 matching passes per level (FP64 and mixed, warm-up + mean of 2)
+        sweep = {}
+        for afrom, passes in ((0, 2), (0, 3), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3), (4, 3),
+                              (6, 3)):
+            m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, passes=passes,
+                         aggressive_from=afrom)
+            r = {"levels": m.n_levels()}
+            for prec in ("fp64", "mixed"):
+                r[prec] = timed_pcg(dict(opts, precision=prec))[1]
+            sweep[f"from{afrom}_passes{passes}"] = r
+        best = min(sweep, key=lambda k: sweep[k]["fp64"]["s"])
+        variants["agglomeration_sweep"] = {"runs": sweep, "best_fp64": best}
+        log(f"[bench] agglomeration sweep: best {best} {sweep[best]}")
+
+        # the two-stage Gauss-Seidel smoother and the DIC coarsest
+        # preconditioner on the headline hierarchy
+        for name, kw in (("gs2_smoother", dict(smoother="gs2")),
                          ("dic_coarsest", dict(coarsest="dic"))):
             t0 = time.perf_counter()
-            m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, **kw)
+            m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, **hier, **kw)
             torch.cuda.synchronize()
-            ts = time.perf_counter() - t0
-            rec = {"setup_s": ts, "levels": m.n_levels()}
+            rec = {"setup_s": time.perf_counter() - t0, "levels": m.n_levels()}
             for prec in ("fp64", "mixed"):
-                vo = dict(opts, precision=prec)
-                m.pcg(b, **vo)
-                vt = []
-                for _ in range(2):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    xv, sv = m.pcg(b, **vo)
-                    torch.cuda.synchronize()
-                    vt.append(time.perf_counter() - t0)
-                vres = m.residual(b, xv)
-                assert sv.converged and vres <= 1e-8, (name, prec, sv, vres)
-                rec[prec] = {"s": float(np.mean(vt)), "iterations": sv.iterations,
-                             "refinements": sv.refinements, "true_residual": vres}
+                rec[prec] = timed_pcg(dict(opts, precision=prec))[1]
             variants[name] = rec
             log(f"[bench] variant {name}: {rec['levels']} levels, fp64 {rec['fp64']['s']:.4f} s "
                 f"({rec['fp64']['iterations']} it), mixed {rec['mixed']['s']:.4f} s")
-
-        # the tail of small levels: pairwise down to level `from`, then 2 or 3
-        # matching passes per level (FP64, one warm-up, best of two)
-        tail = {}
-        for afrom in (3, 4, 5, 6):
-            for passes in (2, 3):
-                m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, passes=passes,
-                             aggressive_from=afrom)
-                m.pcg(b, **opts)
-                vt = []
-                for _ in range(2):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    xv, sv = m.pcg(b, **opts)
-                    torch.cuda.synchronize()
-                    vt.append(time.perf_counter() - t0)
-                assert sv.converged, (afrom, passes, sv)
-                tail[f"from{afrom}_passes{passes}"] = {
-                    "levels": m.n_levels(), "iterations": sv.iterations, "s": float(min(vt))}
-        best = min(tail, key=lambda k: tail[k]["s"])
-        variants["tail_sweep"] = {"runs": tail, "best": best}
-        log(f"[bench] tail sweep: best {best} {tail[best]}")
-        m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
+        m.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps, **hier)
 
         # the non-symmetric solve (PBiCG, diagonal preconditioner) on the
         # convection-diffusion box of the same size (200^3, upwind, Courant 2)
@@ -654,9 +674,10 @@ def main():
         aargs = [torch.from_numpy(ga[k]).to(dev) for k in ("gamma", "weights", "mag_sf", "delta")]
         akw = {k: torch.from_numpy(ga[k]).to(dev) for k in ("diag_bc", "phi", "b_bc")}
         asm = {}
-        for label, hier in (("assemble", False), ("assemble_and_refresh_gamg", True)):
-            if hier:
-                ma.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps)
+        for label, refresh in (("assemble", False), ("assemble_and_refresh_gamg", True)):
+            if refresh:
+                ma.gamg_setup(n_pre=args.sweeps, n_post=args.sweeps,
+                              **HIERARCHIES[args.agglomeration])
             ma.assemble_pressure(*aargs, **akw)
             at = []
             for _ in range(3):
@@ -723,8 +744,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"c3: {args.n}^3 graded hex, {case.n_cells} cells, "
                                f"{case.n_faces} faces, Dirichlet top, N(0,1) rhs",
-                   "solver": f"CG + GAMG V-cycle (pairwise agglomeration, {args.sweeps}+"
-                             f"{args.sweeps} Jacobi sweeps w=0.75, diagonal-CG coarsest)",
+                   "solver": f"CG + GAMG V-cycle ({AGG_TEXT[args.agglomeration]}, "
+                             f"{nlev} levels, {args.sweeps}+{args.sweeps} Jacobi sweeps "
+                             f"w=0.75, diagonal-CG coarsest)",
                    "rel_tol": 1e-8, "x0": "zero"},
         "roofline": {"bound": "hbm", "kernel": "ldu_amul (k_amul<double>)",
                      "achieved": amul_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -734,7 +756,8 @@ def main():
     }
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(case, st.iterations, args.sweeps, t_step)
+        out["cpu_baseline"] = cpu_baseline(case, st.iterations, args.sweeps, t_step,
+                                           hierarchy=hier)
         log(f"[bench] oracle estimate {out['cpu_baseline']['value']:.1f} s per solve")
     m.close()
     print(json.dumps(out))

@@ -28,3 +28,13 @@ def test_cpu_baseline_record_on_a_small_case():
     assert "measured at 1,024 cells" in rec["sample"]
     assert "3 CG iterations with one 1+1-sweep V-cycle" in rec["sample"]
     assert "times the GPU's 10 iterations" in rec["sample"]
+
+
+def test_cpu_baseline_names_the_hierarchy():
+    import bench
+    from meshgen import config_case
+    case = config_case("c3", n=16, nxy=8)
+    rec = bench.cpu_baseline(case, 10, 1, 0.5, sample_iters=2,
+                             hierarchy=bench.HIERARCHIES["aggressive"])
+    assert "'passes': 3, 'aggressive_from': 1" in rec["sample"]
+    assert rec["value"] > 0

@@ -941,9 +941,9 @@ __global__ void k_rop_gather(int32_t nc, const int32_t *__restrict__ start,
 }
 
 // R's columns, and for each entry of R the run of its sources in the sorted
-// pairs (start, count)
-__global__ void k_rop_link(int32_t nc, Sell R, const int64_t *__restrict__ tstart,
-                           const int32_t *__restrict__ tcol, int64_t *rs0, int32_t *rsn) {
+// pairs (start, count): compressed slices
+__global__ void k_rop_link_sell(int32_t nc, Sell R, const int64_t *__restrict__ tstart,
+                                const int32_t *__restrict__ tcol, int64_t *rs0, int32_t *rsn) {
     GRID_STRIDE(c, nc) {
         const int64_t ps = R.iperm[c], o = tstart[c], o1 = tstart[c + 1];
         int q = 0;
@@ -959,10 +959,33 @@ __global__ void k_rop_link(int32_t nc, Sell R, const int64_t *__restrict__ tstar
     }
 }
 
+// the same for CSR
+__global__ void k_rop_link_csr(int32_t nc, Csr R, const int64_t *__restrict__ tstart,
+                               const int32_t *__restrict__ tcol, int64_t *rs0, int32_t *rsn) {
+    GRID_STRIDE(c, nc) {
+        const int64_t o = tstart[c], o1 = tstart[c + 1];
+        int64_t e = R.rptr[c];
+        for (int64_t a = o; a < o1;) {
+            int64_t b = a + 1;
+            while (b < o1 && tcol[b] == tcol[a]) ++b;
+            R.col[e] = tcol[a];
+            rs0[e] = a;
+            rsn[e] = (int32_t)(b - a);
+            ++e;
+            a = b;
+        }
+    }
+}
+
+__global__ void k_widen(int32_t n, const int32_t *__restrict__ a, int64_t *__restrict__ b) {
+    GRID_STRIDE(i, n) b[i] = a[i];
+}
+
 // values of R (and of its A^T form) from the level's coefficients: each entry
 // sums its sources in member order, (1 - omega) for a diagonal and
 // -omega a / D_j for an entry a of column j
-__global__ void k_rop_values(int64_t nnz, Sell R, const int64_t *__restrict__ rs0,
+template <class M>
+__global__ void k_rop_values(int64_t nnz, M R, const int64_t *__restrict__ rs0,
                              const int32_t *__restrict__ rsn, const int64_t *__restrict__ src,
                              const double *__restrict__ aval, const double *__restrict__ avalT,
                              const double *__restrict__ D, double omega) {
@@ -1001,7 +1024,7 @@ static bool rop_cycle(const ldu_gamg_opts &o) {
 // first Jacobi sweep from zero e_c = omega r_c / D_c when ec_first is given
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_vc_rrestrict(SellView<T> R, const T *__restrict__ r, T *__restrict__ rc,
+k_vc_rrestrict_cmp(SellView<T> R, const T *__restrict__ r, T *__restrict__ rc,
                T *__restrict__ ec_first, const T *__restrict__ Dc, T omega,
                const DevScalars *ds) {
     if (vc_skip(ds)) return;
@@ -1019,6 +1042,75 @@ k_vc_rrestrict(SellView<T> R, const T *__restrict__ r, T *__restrict__ rc,
             if (ec_first) ec_first[c] = omega * acc / dc;
         }
     });
+}
+
+// r_c = R r, and the coarse level's first Jacobi sweep from zero
+// e_c = omega r_c / D_c when ec_first is given.  G lanes share a row: lane g
+// of the group sums the row's entries g, g + G, g + 2G, ... in order, then
+// the group adds its G partial sums by a fixed butterfly (every lane ends
+// with the same total).  A wave covers 64 / G consecutive rows.  The order
+// is fixed, so results are reproducible; it is not the row's column order,
+// which R's results never had to follow (R's rows are sums the oracle forms
+// in two steps, residual then restriction).
+template <int G, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_vc_rrestrict_csr(CsrView<T> R, const T *__restrict__ r, T *__restrict__ rc,
+               T *__restrict__ ec_first, const T *__restrict__ Dc, T omega,
+               const DevScalars *ds) {
+    if (vc_skip(ds)) return;
+    constexpr int RPW = kWave / G;
+    constexpr int U = kCsrBatch;
+    const int lane = threadIdx.x & 63;
+    const int g = lane % G;
+    const int64_t chunks = (R.n + RPW - 1) / RPW;
+    for_each_slice(chunks, [&](int64_t s) {
+        const int64_t c = s * RPW + lane / G;
+        T acc = T(0), dc = T(1);
+        if (c < R.n) {
+            // the coarse diagonal is loaded before the row, so its round
+            // trip overlaps the row's gathers
+            if (ec_first && g == 0) dc = Dc[c];
+            const int64_t e1 = R.rptr[c + 1];
+            for (int64_t k0 = R.rptr[c] + g; k0 < e1; k0 += (int64_t)G * U) {
+                int32_t cc[U];
+                T vv[U], xv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t k = k0 + (int64_t)u * G;
+                    if (k < e1) {
+                        cc[u] = __builtin_nontemporal_load(R.col + k);
+                        vv[u] = __builtin_nontemporal_load(R.val + k);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (k0 + (int64_t)u * G < e1) xv[u] = r[cc[u]];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (k0 + (int64_t)u * G < e1) acc = acc + vv[u] * xv[u];
+            }
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc = acc + __shfl_xor(acc, off);
+        if (c < R.n && g == 0) {
+            rc[c] = acc;
+            if (ec_first) ec_first[c] = omega * acc / dc;
+        }
+    });
+}
+
+template <typename T>
+static void launch_rrestrict_csr(const CsrView<T> &R, const T *r, T *rc, T *ec_first, const T *Dc,
+                             T omega, const DevScalars *ds, hipStream_t st) {
+    const int64_t chunks = (R.n + kWave / R.group - 1) / (kWave / R.group);
+    const int G = stream_grid_slices(chunks);
+    switch (R.group) {
+    case 1: k_vc_rrestrict_csr<1, T><<<G, kBlock, 0, st>>>(R, r, rc, ec_first, Dc, omega, ds); break;
+    case 2: k_vc_rrestrict_csr<2, T><<<G, kBlock, 0, st>>>(R, r, rc, ec_first, Dc, omega, ds); break;
+    case 4: k_vc_rrestrict_csr<4, T><<<G, kBlock, 0, st>>>(R, r, rc, ec_first, Dc, omega, ds); break;
+    case 8: k_vc_rrestrict_csr<8, T><<<G, kBlock, 0, st>>>(R, r, rc, ec_first, Dc, omega, ds); break;
+    default: k_vc_rrestrict_csr<16, T><<<G, kBlock, 0, st>>>(R, r, rc, ec_first, Dc, omega, ds);
+    }
 }
 
 // c = P e_c; s = (c . t) / (c . A c), or 1 when c.Ac is ~0
@@ -1504,6 +1596,17 @@ template <>
 SellView<double> rview<double>(const Level &L, bool tr) { return L.R.view(tr); }
 template <>
 SellView<float> rview<float>(const Level &L, bool tr) { return L.R.view32(tr); }
+template <typename T>
+static CsrView<T> rcview(const Level &L, bool tr);
+template <>
+CsrView<double> rcview<double>(const Level &L, bool tr) { return L.Rc.view(tr); }
+template <>
+CsrView<float> rcview<float>(const Level &L, bool tr) { return L.Rc.view32(tr); }
+// R's values of this precision exist (either layout)
+template <typename T>
+static bool has_rop(const Level &L, bool tr) {
+    return rview<T>(L, tr).val != nullptr || rcview<T>(L, tr).val != nullptr;
+}
 
 template <typename T>
 static T *lvec(Level &L, int which);
@@ -1565,8 +1668,8 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
     const T omega = (T)c.o->omega;
     const bool gs = c.o->smoother == LDU_SMOOTH_GS2;
     T *w1 = lvec<T>(L, 4);
-    const SellView<T> R = rview<T>(L, c.tr);
-    const bool rop = rop_cycle(*c.o) && L.r_ready && L.r_omega == c.o->omega && R.val;
+    const bool rop = rop_cycle(*c.o) && L.r_ready && L.r_omega == c.o->omega &&
+                     has_rop<T>(L, c.tr);
     // without correction scaling, on levels small enough to be bound by launch
     // latency, the coarse level applies e += P e_c itself (a scatter through
     // the member lists: on large levels the gather form of k_vc_correct moves
@@ -1594,14 +1697,20 @@ static T *vcycle(const VCtx &c, size_t l, const T *r, const T *rdot = nullptr,
     // the coarse level will form it in its own correction (a large
     // non-coarsest level whose down leg also runs through R)
     const bool c_defers = l + 2 < h->levels.size() && rop && C.r_ready &&
-                          C.r_omega == c.o->omega && rview<T>(C, c.tr).val &&
+                          C.r_omega == c.o->omega && has_rop<T>(C, c.tr) &&
                           C.n > kFuseCorrRows;
     const bool c_first = !gs && c.o->n_pre > 0 && l + 2 < h->levels.size() && !c_defers;
     T *ec_first = c_first ? lvec<T>(C, 1) : nullptr;
     if (rop) {
         // residual and restriction in one pass over R (t is not formed)
-        k_vc_rrestrict<T><<<stream_grid_slices(R.nslices), kBlock, 0, st>>>(
-            R, r, rc, ec_first, lview<T>(C, c.tr).diag, omega, h->dev);
+        if (L.R.sptr) {
+            const SellView<T> R = rview<T>(L, c.tr);
+            k_vc_rrestrict_cmp<T><<<stream_grid_slices(R.nslices), kBlock, 0, st>>>(
+                R, r, rc, ec_first, lview<T>(C, c.tr).diag, omega, h->dev);
+        } else {
+            launch_rrestrict_csr<T>(rcview<T>(L, c.tr), r, rc, ec_first, lview<T>(C, c.tr).diag,
+                                    omega, h->dev, st);
+        }
     } else {
         if (A.pdeg) k_vc_resid<true, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
         else k_vc_resid<false, T><<<G, kBlock, 0, st>>>(A, r, e, t, h->dev);
@@ -1670,10 +1779,35 @@ static void rop_structure(ldu_t *h, size_t l, hipStream_t st) {
     int32_t *rdeg = tmp.get<int32_t>(C.n);
     k_rop_gather<<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.aggStart, L.aggCells, L.A, tstart, tcol,
                                                 L.r_src, rdeg);
-    build_sliced_rows(L.R, C.n, rdeg, h->gamg_arena, st);
-    L.r_src0 = h->gamg_arena.get<int64_t>(L.R.nnz);
-    L.r_srcn = h->gamg_arena.get<int32_t>(L.R.nnz);
-    k_rop_link<<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.R, tstart, tcol, L.r_src0, L.r_srcn);
+    if (C.n > kCsrMaxRows) {
+        build_sliced_rows(L.R, C.n, rdeg, h->gamg_arena, st);
+        L.r_src0 = h->gamg_arena.get<int64_t>(L.R.nnz);
+        L.r_srcn = h->gamg_arena.get<int32_t>(L.R.nnz);
+        k_rop_link_sell<<<grid_n(C.n), kBlock, 0, st>>>(C.n, L.R, tstart, tcol, L.r_src0,
+                                                        L.r_srcn);
+    } else {
+        Csr &R = L.Rc;
+        R = Csr{};
+        R.n = C.n;
+        R.rptr = h->gamg_arena.get<int64_t>((size_t)C.n + 1);
+        int64_t *rdeg64 = tmp.get<int64_t>(C.n);
+        k_widen<<<grid_n(C.n), kBlock, 0, st>>>(C.n, rdeg, rdeg64);
+        exclusive_scan_i64(rdeg64, R.rptr, C.n, tmp, st);
+        HIP_CHECK(hipMemcpyAsync(&R.nnz, R.rptr + C.n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                 st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        R.col = h->gamg_arena.get<int32_t>(R.nnz);
+        R.val = h->gamg_arena.get<double>(R.nnz);
+        R.valT = h->gamg_arena.get<double>(R.nnz);
+        // lanes per row: the power of two nearest mean length / entries per lane
+        const double per = (double)R.nnz / std::max<int32_t>(C.n, 1) / kCsrEntriesPerLane;
+        int g = 1;
+        while (g < 16 && 2.0 * g <= per * 1.41421356) g *= 2;
+        R.group = g;
+        L.r_src0 = h->gamg_arena.get<int64_t>(R.nnz);
+        L.r_srcn = h->gamg_arena.get<int32_t>(R.nnz);
+        k_rop_link_csr<<<grid_n(C.n), kBlock, 0, st>>>(C.n, R, tstart, tcol, L.r_src0, L.r_srcn);
+    }
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(st));  // tmp is released after this point
     L.r_ready = false;
@@ -1681,13 +1815,16 @@ static void rop_structure(ldu_t *h, size_t l, hipStream_t st) {
 
 // R's values (and their FP32 copies, when present) for the given omega
 static void rop_values(Level &L, double omega, hipStream_t st) {
-    Sell &R = L.R;
-    k_rop_values<<<grid_n(R.nnz), kBlock, 0, st>>>(R.nnz, R, L.r_src0, L.r_srcn, L.r_src, L.A.val,
-                                                  L.A.valT, L.A.diag, omega);
-    if (R.val32) {
-        k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.val, R.val32, R.nnz);
-        k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.valT, R.valT32, R.nnz);
-    }
+    auto fill = [&](auto &R) {
+        k_rop_values<<<grid_n(R.nnz), kBlock, 0, st>>>(R.nnz, R, L.r_src0, L.r_srcn, L.r_src,
+                                                      L.A.val, L.A.valT, L.A.diag, omega);
+        if (R.val32) {
+            k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.val, R.val32, R.nnz);
+            k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.valT, R.valT32, R.nnz);
+        }
+    };
+    if (L.R.sptr) fill(L.R);
+    else fill(L.Rc);
     HIP_CHECK(hipGetLastError());
     L.r_omega = omega;
     L.r_ready = true;
@@ -1701,16 +1838,18 @@ static void ensure_rop(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
     const bool f32 = h->L0.A.val32 != nullptr;
     for (size_t l = 0; l + 1 < h->levels.size(); ++l) {
         Level &L = h->levels[l];
-        Sell &R = L.R;
-        if (!R.sptr) rop_structure(h, l, st);
+        if (!L.R.sptr && !L.Rc.rptr) rop_structure(h, l, st);
         const bool fresh = L.r_ready && L.r_omega == o.omega;
         if (!fresh) rop_values(L, o.omega, st);
-        if (f32 && !R.val32) {  // values are current: only the FP32 copies are new
+        auto f32_copies = [&](auto &R) {
+            if (!f32 || R.val32) return;  // values are current: only the FP32 copies are new
             R.val32 = h->gamg_arena.get<float>(R.nnz);
             R.valT32 = h->gamg_arena.get<float>(R.nnz);
             k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.val, R.val32, R.nnz);
             k_rop_f32<<<grid_n(R.nnz), kBlock, 0, st>>>(R.valT, R.valT32, R.nnz);
-        }
+        };
+        if (L.R.sptr) f32_copies(L.R);
+        else f32_copies(L.Rc);
         HIP_CHECK(hipGetLastError());
     }
 }
@@ -1718,7 +1857,8 @@ static void ensure_rop(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st) {
 // new level coefficients: R's values follow at once (same omega)
 static void refresh_rop(ldu_t *h, hipStream_t st) {
     for (size_t l = 0; l + 1 < h->levels.size(); ++l)
-        if (h->levels[l].R.sptr && h->levels[l].r_ready) rop_values(h->levels[l], h->levels[l].r_omega, st);
+        if ((h->levels[l].R.sptr || h->levels[l].Rc.rptr) && h->levels[l].r_ready)
+            rop_values(h->levels[l], h->levels[l].r_omega, st);
 }
 
 static VCtx make_ctx(ldu_t *h, const ldu_gamg_opts &o, bool tr, hipStream_t st) {

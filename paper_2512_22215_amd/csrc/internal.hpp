@@ -167,6 +167,51 @@ struct Sell {
     }
 };
 
+// rows stored one after another, each row's entries contiguous and in
+// column order (the restriction operators R)
+template <typename T>
+struct CsrView {
+    int32_t n;
+    const int64_t *rptr;
+    const int32_t *col;
+    const T *val;
+    int group;  // lanes that share a row in the product kernel
+};
+
+struct Csr {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int64_t *rptr = nullptr;  // [n + 1]
+    int32_t *col = nullptr;
+    double *val = nullptr, *valT = nullptr;
+    float *val32 = nullptr, *valT32 = nullptr;
+    int group = 1;
+    __host__ __device__ CsrView<double> view(bool transpose) const {
+        return {n, rptr, col, transpose ? valT : val, group};
+    }
+    __host__ __device__ CsrView<float> view32(bool transpose) const {
+        return {n, rptr, col, transpose ? valT32 : val32, group};
+    }
+};
+
+// lanes per row of a CSR product: the power of two nearest the mean row
+// length over this many entries per lane, from 1 to 16 (every lane then
+// loads its few entries at once, so a long row costs one round trip instead
+// of a chain of batches)
+#ifndef LDU_CSR_ENTRIES_PER_LANE
+#define LDU_CSR_ENTRIES_PER_LANE 2
+#endif
+constexpr int kCsrEntriesPerLane = LDU_CSR_ENTRIES_PER_LANE;
+constexpr int kCsrBatch = 8;  // entries a lane loads before its gathers
+// restriction operators with at most this many rows are stored in CSR: there
+// a row's lanes load its entries in one round trip.  Above it compressed
+// slices win: a lane per row keeps the matrix stream coalesced, and there
+// are enough rows to hide the chain of batches
+#ifndef LDU_R_CSR_MAX_ROWS
+#define LDU_R_CSR_MAX_ROWS 300000
+#endif
+constexpr int64_t kCsrMaxRows = LDU_R_CSR_MAX_ROWS;
+
 struct Level {
     int32_t n = 0;
     int64_t nf = 0;
@@ -185,8 +230,10 @@ struct Level {
     int32_t *cfFace = nullptr, *ciFace = nullptr;
     // the down leg of a cycle with one Jacobi pre-sweep from zero as one
     // operator: R = P^T (I - omega A D^-1), a row per coarse cell over this
-    // level's columns, in compressed slices (valT: the same for A^T)
+    // level's columns (valT: the same for A^T), in compressed slices (R) when
+    // it has more than kCsrMaxRows rows, else in CSR (Rc)
     Sell R;
+    Csr Rc;
     int64_t *r_src = nullptr;             // sources of R's entries, by entry in runs:
     int64_t *r_src0 = nullptr;            //   first source of each entry of R
     int32_t *r_srcn = nullptr;            //   and their count (source -1: a diagonal)

@@ -666,6 +666,8 @@ k_vc_zero(int32_t n, int64_t S, T *__restrict__ e, const DevScalars *ds) {
 // rdot . e_out (the preconditioned CG's r . z, saving a pass over both)
 // The finer level's unscaled correction e_f += P e_c, applied by the kernel
 // that produces e_c: row a adds its value to the members of aggregate a.
+constexpr int kCorrBatch = 8;  // aggregate members a fused correction handles at once
+
 template <typename T>
 struct FineCorr {
     T *e;
@@ -673,11 +675,23 @@ struct FineCorr {
     __device__ __forceinline__ void operator()(int32_t a, T v) const {
         apply(start[a], start[a + 1], v);
     }
-    // members k0..k1-1 of the aggregate (bounds loaded ahead by the caller)
+    // members k0..k1-1 of the aggregate (bounds loaded ahead by the caller),
+    // kCorrBatch at a time: their indices, then their values, are loaded
+    // together before any store (the members are distinct cells), so an
+    // aggregate of several passes costs a few round trips, not one per member
     __device__ __forceinline__ void apply(int32_t k0, int32_t k1, T v) const {
-        for (int32_t k = k0; k < k1; ++k) {
-            const int32_t j = cells[k];
-            e[j] = e[j] + v;
+        for (int32_t k = k0; k < k1; k += kCorrBatch) {
+            int32_t j[kCorrBatch];
+            T ev[kCorrBatch];
+#pragma unroll
+            for (int u = 0; u < kCorrBatch; ++u)
+                if (k + u < k1) j[u] = cells[k + u];
+#pragma unroll
+            for (int u = 0; u < kCorrBatch; ++u)
+                if (k + u < k1) ev[u] = e[j[u]];
+#pragma unroll
+            for (int u = 0; u < kCorrBatch; ++u)
+                if (k + u < k1) e[j[u]] = ev[u] + v;
         }
     }
 };
@@ -695,13 +709,15 @@ k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
     double acc[1] = {0.0};
     // with CORR the aggregate bounds of row i are loaded before the row's
     // product, so their round trip overlaps its gathers
-    auto finish = [&](int32_t i, T y, int32_t k0, int32_t k1) {
-        const T zi = e[i] + omega * (r[i] - y) / A.diag[i];
+    auto finish = [&](int32_t i, T y, T ri, T di, T ei, int32_t k0, int32_t k1) {
+        const T zi = ei + omega * (ri - y) / di;
         eo[i] = zi;
         if constexpr (DOT) acc[0] += (double)rdot[i] * (double)zi;
         if constexpr (CORR) fc.apply(k0, k1, zi);
     };
     if constexpr (CMP) {
+        // the row's own values (r, D, e) are loaded before its entries, so
+        // their round trip overlaps the entry loads and gathers
         for_each_cmp_slice(A, [&](int64_t, const CmpHead &hd) {
             if (hd.row >= 0) {
                 const int32_t i = hd.row;
@@ -710,10 +726,11 @@ k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
                     k0 = fc.start[i];
                     k1 = fc.start[i + 1];
                 }
-                T y = A.diag[i] * e[i];  // the row's order: diagonal, then columns
+                const T ri = r[i], di = A.diag[i], ei = e[i];
+                T y = di * ei;  // the row's order: diagonal, then columns
                 cmp_entries_at<kCmpBatch>(A, hd.b0, hd.w, lane, Direct<T>{e},
                                           [&](int32_t, T v, T xv) { y = y + v * xv; });
-                finish(i, y, k0, k1);
+                finish(i, y, ri, di, ei, k0, k1);
             }
         });
     } else {
@@ -726,7 +743,8 @@ k_vc_jacobi(SellView<T> A, const T *__restrict__ r, const T *__restrict__ e,
                     k0 = fc.start[i];
                     k1 = fc.start[i + 1];
                 }
-                finish(i, sell_row<CMP>(A, s, lane, i, Direct<T>{e}), k0, k1);
+                const T y = sell_row<CMP>(A, s, lane, i, Direct<T>{e});
+                finish(i, y, r[i], A.diag[i], e[i], k0, k1);
             }
         });
     }
@@ -791,7 +809,20 @@ k_vc_restrict(int32_t nc, const int32_t *__restrict__ start, const int32_t *__re
     GRID_STRIDE(a, nc) {
         const T dc = ec_first ? Dc[a] : T(1);  // loaded ahead of the member sums
         T s = T(0);
-        for (int32_t k = start[a]; k < start[a + 1]; ++k) s += t[cells[k]];
+        const int32_t k1 = start[a + 1];
+        for (int32_t k = start[a]; k < k1; k += kCorrBatch) {  // loads of a batch together
+            int32_t j[kCorrBatch];
+            T tv[kCorrBatch];
+#pragma unroll
+            for (int u = 0; u < kCorrBatch; ++u)
+                if (k + u < k1) j[u] = cells[k + u];
+#pragma unroll
+            for (int u = 0; u < kCorrBatch; ++u)
+                if (k + u < k1) tv[u] = t[j[u]];
+#pragma unroll
+            for (int u = 0; u < kCorrBatch; ++u)
+                if (k + u < k1) s += tv[u];
+        }
         rc[a] = s;
         // the coarse level's first Jacobi sweep from zero, e_c = omega r_c / D_c
         if (ec_first) ec_first[a] = omega * s / dc;

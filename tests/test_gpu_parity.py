@@ -436,6 +436,47 @@ def test_pcg_gamg_matches_oracle(name):
 ONE_SWEEP = dict(n_pre=1, n_post=1, scale_correction=0)
 
 
+# meshes whose restriction operators have short to long rows, so the CSR
+# product runs with 2, 4, 8 and 16 lanes per row (the power of two nearest
+# the mean row length over two entries per lane): a chain (rows of about 4
+# entries), a plane (about 8), a box (about 13) and a box with three matching
+# passes per level below level 1 (about 50)
+R_LANE_CASES = {
+    "chain": (dict(nx=3000, ny=1, nz=1), {}),
+    "plane": (dict(nx=70, ny=60, nz=1), {}),
+    "box": (dict(nx=22, ny=20, nz=18), {}),
+    "box_aggressive": (dict(nx=22, ny=20, nz=18), dict(passes=3, aggressive_from=1)),
+}
+
+
+@pytest.mark.parametrize("name", list(R_LANE_CASES))
+def test_csr_restriction_lane_groups(name):
+    """The one-pass down leg through R in CSR, for row lengths that select
+    different numbers of lanes per row: CG + V-cycle (FP64, forward and
+    transposed) against the oracle's two-step cycle, and the mixed form
+    refined to 1e-12."""
+    dims, hier = R_LANE_CASES[name]
+    c = box_case(dims["nx"], dims["ny"], dims["nz"], coeff="lognormal", dirichlet_x0=1.0,
+                 seed=13)
+    A = O.Ldu.from_case(c)
+    m = _lib().from_case(c)
+    m.gamg_setup(**ONE_SWEEP, **hier)
+    g = O.Gamg(A, **hier)
+    assert m.n_levels() == g.n_levels
+    b = c.rhs[0]
+    x, st = m.pcg(_t(b), precond=2, rel_tol=1e-8, history=1000)
+    ref = g.pcg(b, tol=1e-8, n_pre=1, n_post=1)
+    assert st.converged and st.iterations == ref.iterations
+    assert hist_close(st.history, ref.history, 1e-8)
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    xt, stt = m.adjoint(_t(b), solver="pcg", precond=2, rel_tol=1e-8)
+    reft = g.pcg(b, tol=1e-8, n_pre=1, n_post=1, transpose=True)
+    assert stt.converged and stt.iterations == reft.iterations
+    xm, sm = m.pcg(_t(b), precond=2, rel_tol=1e-12, precision="mixed")
+    assert sm.converged and true_res(c, xm.cpu().numpy()) <= 1e-12
+    m.close()
+
+
 @pytest.mark.parametrize("name", ["ragged", "c5s", "nonsym", "c3s"])
 def test_one_sweep_cycles_fuse_the_down_leg(name):
     """One Jacobi pre-sweep from zero and no correction scaling: each level's

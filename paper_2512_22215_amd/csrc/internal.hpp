@@ -234,6 +234,12 @@ struct Level {
     // it has more than kCsrMaxRows rows, else in CSR (Rc)
     Sell R;
     Csr Rc;
+    // on a plain-slice level whose R would need compressed slices, the down
+    // leg runs over this level's own slices instead: t = (I - omega A D^-1) r
+    // with the values -omega a_ij / D_j stored at A's positions (ah; ahT the
+    // same for A^T; padding 0), then the member sums of t
+    double *ah = nullptr, *ahT = nullptr;
+    float *ah32 = nullptr, *ahT32 = nullptr;
     int64_t *r_src = nullptr;             // sources of R's entries, by entry in runs:
     int64_t *r_src0 = nullptr;            //   first source of each entry of R
     int32_t *r_srcn = nullptr;            //   and their count (source -1: a diagonal)

@@ -480,6 +480,59 @@ def test_csr_restriction_lane_groups(name):
     m.close()
 
 
+@pytest.mark.parametrize("hier", [{}, dict(passes=3, aggressive_from=1)],
+                         ids=["pairwise", "aggressive"])
+def test_scaled_slice_down_leg(hier):
+    """A plain-slice level with more than 300,000 coarse rows takes its down
+    leg over its own slices, t = (I - w A D^-1) r with the values -w a_ij / D_j
+    (16-bit columns included), then the member sums of t.  On a 720,000-cell
+    box (level 1: about 330,000 cells) against the oracle's two-step cycle:
+    V-cycles at two values of w (the second recomputes the values), CG +
+    V-cycle forward and transposed, the mixed form to 1e-10, and a V-cycle
+    after new coefficients."""
+    from meshgen import assemble_diag
+    c = box_case(100, 90, 80, coeff="lognormal", dirichlet_x0=1.0, seed=17)
+    A = O.Ldu.from_case(c)
+    m = _lib().from_case(c)
+    m.gamg_setup(**ONE_SWEEP, **hier)
+    g = O.Gamg(A, **hier)
+    assert m.n_levels() == g.n_levels
+    # the case takes the scaled-slice path: plain slices on level 0, a coarse
+    # level above the 300,000 rows up to which R is stored in CSR
+    assert m.layout(0)["compressed"] is False and m.layout(0)["col16"] is True
+    assert g.level(1).n > 300000
+    r = np.random.default_rng(43).standard_normal(c.n_cells)
+    # (the agglomeration settings go with every call: a call whose settings
+    # differ from the cached hierarchy's builds a new one)
+    for omega in (0.75, 0.6, 0.75):
+        e = m.vcycle(_t(r), omega=omega, **ONE_SWEEP, **hier).cpu().numpy()
+        ref = g.vcycle(r, n_pre=1, n_post=1, omega=omega, scale=False)
+        assert np.linalg.norm(e - ref) <= 1e-11 * np.linalg.norm(ref), omega
+    b = c.rhs[0]
+    m.gamg_setup(**ONE_SWEEP, **hier)
+    x, st = m.pcg(_t(b), precond=2, rel_tol=1e-8, history=500)
+    ref = g.pcg(b, tol=1e-8, n_pre=1, n_post=1)
+    assert st.converged and st.iterations == ref.iterations
+    assert hist_close(st.history, ref.history, 1e-8)
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    xt, stt = m.adjoint(_t(b), solver="pcg", precond=2, rel_tol=1e-8)
+    reft = g.pcg(b, tol=1e-8, n_pre=1, n_post=1, transpose=True)
+    assert stt.converged and stt.iterations == reft.iterations
+    assert np.linalg.norm(xt.cpu().numpy() - reft.x) <= 1e-9 * np.linalg.norm(reft.x)
+    xm, sm = m.pcg(_t(b), precond=2, rel_tol=1e-10, precision="mixed")
+    assert sm.converged and true_res(c, xm.cpu().numpy()) <= 1e-10
+    # new face coefficients, the Dirichlet part of the diagonal kept
+    a_bc = assemble_diag(c.n_cells, c.owner, c.neighbour, c.upper, c.lower) - c.diag
+    a2 = c.upper * np.exp(0.3 * np.random.default_rng(44).standard_normal(c.n_faces))
+    d2 = assemble_diag(c.n_cells, c.owner, c.neighbour, a2, a2, a_bc)
+    m.set_coeffs(_t(d2), _t(a2), _t(a2))
+    g.set_values(d2, a2, a2)
+    e = m.vcycle(_t(r), **ONE_SWEEP, **hier).cpu().numpy()
+    ref = g.vcycle(r, n_pre=1, n_post=1, scale=False)
+    assert np.linalg.norm(e - ref) <= 1e-11 * np.linalg.norm(ref)
+    m.close()
+
+
 @pytest.mark.parametrize("name", ["ragged", "c5s", "nonsym", "c3s"])
 def test_one_sweep_cycles_fuse_the_down_leg(name):
     """One Jacobi pre-sweep from zero and no correction scaling: each level's

@@ -533,6 +533,37 @@ def test_scaled_slice_down_leg(hier):
     m.close()
 
 
+@pytest.mark.parametrize("hier", [{}, dict(passes=3, aggressive_from=1)],
+                         ids=["pairwise", "aggressive"])
+def test_scaled_slice_down_leg_nonsymmetric(hier):
+    """The scaled-slice down leg on a non-symmetric 720,000-cell box, where
+    the values for A and for A^T differ: a V-cycle and standalone GAMG
+    (forward, and on A^T through the adjoint solve) against the oracle."""
+    c = box_case(100, 90, 80, coeff="lognormal", nonsym=0.6, dirichlet_x0=1.0, seed=19)
+    assert not np.array_equal(c.upper, c.lower)
+    A = O.Ldu.from_case(c)
+    m = _lib().from_case(c)
+    m.gamg_setup(**ONE_SWEEP, **hier)
+    g = O.Gamg(A, **hier)
+    assert m.layout(0)["compressed"] is False and g.level(1).n > 300000
+    r = np.random.default_rng(45).standard_normal(c.n_cells)
+    e = m.vcycle(_t(r), **ONE_SWEEP, **hier).cpu().numpy()
+    ref = g.vcycle(r, n_pre=1, n_post=1, scale=False)
+    assert np.linalg.norm(e - ref) <= 1e-11 * np.linalg.norm(ref)
+    b = c.rhs[0]
+    for tr in (False, True):
+        if tr:
+            x, st = m.adjoint(_t(b), solver="gamg", rel_tol=1e-8, history=100, **ONE_SWEEP,
+                              **hier)
+        else:
+            x, st = m.gamg(_t(b), rel_tol=1e-8, history=100, **ONE_SWEEP, **hier)
+        ref = g.solve(b, tol=1e-8, n_pre=1, n_post=1, scale=False, transpose=tr)
+        assert st.converged and st.iterations == ref.iterations, tr
+        assert hist_close(st.history, ref.history, 1e-8), tr
+        assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x), tr
+    m.close()
+
+
 @pytest.mark.parametrize("name", ["ragged", "c5s", "nonsym", "c3s"])
 def test_one_sweep_cycles_fuse_the_down_leg(name):
     """One Jacobi pre-sweep from zero and no correction scaling: each level's

@@ -742,10 +742,13 @@ def test_oversized_coarsest_level_is_refused_at_setup():
 def test_pbicg_matches_oracle(name, precond):
     """PBiCG (fused Amul + Tmul) against the oracle: forward and transposed
     solves.  The products are bit-exact and only the dot products' summation
-    orders differ, so the first ten residuals agree to 1e-8; later, BiCG's
-    near-breakdowns (it minimises nothing) amplify those roundings, so the
-    paths are compared by iteration count (within 10%) and by the solutions
-    (both at the tolerance, and within 1e-8 of each other)."""
+    orders differ, so the first ten residuals agree to 1e-11 (measured: 2e-13
+    at most); later, BiCG's near-breakdowns (it minimises nothing) amplify
+    those roundings, and a residual that crosses the tolerance within that
+    rounding may stop one iteration earlier or later (measured: 0 or 1 on
+    every case), so the paths are compared by iteration count (within one)
+    and by the solutions (both at the tolerance, and within 1e-8 of each
+    other)."""
     from meshgen import config_case
     c = CASES["nonsym"] if name == "nonsym" else config_case("c5u", n=24)
     A = O.Ldu.from_case(c)
@@ -760,13 +763,12 @@ def test_pbicg_matches_oracle(name, precond):
             xg = x.cpu().numpy()
         ref = O.pbicg(A, c.rhs[0], tol=1e-10, precond=bool(precond), transpose=tr)
         assert ref.status == O.OK and st.converged
-        assert abs(st.iterations - ref.iterations) <= max(1, ref.iterations // 10), \
-            (st.iterations, ref.iterations)
+        assert abs(st.iterations - ref.iterations) <= 1, (st.iterations, ref.iterations)
         h = np.asarray(st.history)
         dev = np.abs(h[:11] - ref.history[:11]) / ref.history[:11]
         print(f"{name} precond {precond} transpose {tr}: {st.iterations} vs "
               f"{ref.iterations} iterations, history deviation over 10 steps {dev.max():.2e}")
-        assert dev.max() <= 1e-8
+        assert dev.max() <= 1e-11
         bt = O.tmul(A, xg) if tr else O.amul(A, xg)
         assert np.linalg.norm(c.rhs[0] - bt) <= 1e-10 * np.linalg.norm(c.rhs[0])
         assert np.linalg.norm(xg - ref.x) <= 1e-8 * np.linalg.norm(ref.x)

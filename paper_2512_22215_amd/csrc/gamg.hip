@@ -2086,15 +2086,19 @@ k_pg_start(int32_t n, int64_t S, const double *__restrict__ r, const double *__r
 
 struct EpiRho {
     __device__ bool active(const DevScalars *ds) const { return !ds->done; }
-    __device__ void operator()(const double *t, DevScalars *ds) const { ds->rho = t[0]; }
+    __device__ void operator()(const double *t, DevScalars *ds) const {
+        ds->rho = t[0];
+        ds->x_pending = 0;
+    }
 };
 
-// x += alpha p; r -= alpha q; ||r||^2
+// r -= alpha q; ||r||^2.  The iteration's x += alpha p waits for the
+// direction update, which reads p anyway (k_pg_p), or, when the solve stops
+// in between, for k_pg_x_pending: one read of p per iteration instead of two.
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
-k_pg_update(int32_t n, int64_t S, double *__restrict__ x, double *__restrict__ r,
-            const double *__restrict__ p, const double *__restrict__ q, double *partials,
-            const DevScalars *ds) {
+k_pg_update(int32_t n, int64_t S, double *__restrict__ r, const double *__restrict__ q,
+            double *partials, const DevScalars *ds) {
     if (ds->done) return;
     const double alpha = ds->alpha;
     const int lane = threadIdx.x & 63;
@@ -2102,13 +2106,26 @@ k_pg_update(int32_t n, int64_t S, double *__restrict__ x, double *__restrict__ r
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
         if (i < n) {
-            vst<NT>(x + i, vld<NT>(x + i) + alpha * vld<NT>(p + i));
             const double ri = vld<NT>(r + i) - alpha * vld<NT>(q + i);
             vst<NT>(r + i, ri);
             acc[0] += ri * ri;
         }
     });
     block_partials<1>(acc, partials);
+}
+
+// x += alpha p when the stopped solve's last iteration still owes it (the
+// same expression k_pg_p applies)
+__global__ void __launch_bounds__(kBlock)
+k_pg_x_pending(int32_t n, int64_t S, double *__restrict__ x, const double *__restrict__ p,
+               const DevScalars *ds) {
+    if (!ds->x_pending) return;
+    const double alpha = ds->alpha;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) x[i] = x[i] + alpha * p[i];
+    });
 }
 
 // rho' = r.z; beta = rho'/rho
@@ -2130,20 +2147,26 @@ struct EpiBeta {
     __device__ void operator()(const double *t, DevScalars *ds) const {
         ds->beta = t[0] / ds->rho;
         ds->rho = t[0];
+        ds->x_pending = 0;  // k_pg_p applies it next
     }
 };
 
+// x += alpha p (the iteration's solution update, deferred from k_pg_update);
 // p = z + beta p
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
-k_pg_p(int32_t n, int64_t S, const double *__restrict__ z, double *__restrict__ p,
-       const DevScalars *ds) {
+k_pg_p(int32_t n, int64_t S, double *__restrict__ x, const double *__restrict__ z,
+       double *__restrict__ p, const DevScalars *ds) {
     if (ds->done) return;
-    const double beta = ds->beta;
+    const double alpha = ds->alpha, beta = ds->beta;
     const int lane = threadIdx.x & 63;
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
-        if (i < n) vst<NT>(p + i, vld<NT>(z + i) + beta * vld<NT>(p + i));
+        if (i < n) {
+            const double pi = vld<NT>(p + i);
+            vst<NT>(x + i, vld<NT>(x + i) + alpha * pi);
+            vst<NT>(p + i, vld<NT>(z + i) + beta * pi);
+        }
     });
 }
 
@@ -2188,23 +2211,25 @@ int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, b
             for (int k = 0; k < every; ++k) {
                 launch_pcg_q(h, A, h->p, h->q, G, st);
                 if (nt)
-                    k_pg_update<true><<<G, kBlock, 0, st>>>(n, S, x, h->r, h->p, h->q,
-                                                            h->partials, h->dev);
+                    k_pg_update<true><<<G, kBlock, 0, st>>>(n, S, h->r, h->q, h->partials,
+                                                            h->dev);
                 else
-                    k_pg_update<false><<<G, kBlock, 0, st>>>(n, S, x, h->r, h->p, h->q,
-                                                             h->partials, h->dev);
+                    k_pg_update<false><<<G, kBlock, 0, st>>>(n, S, h->r, h->q, h->partials,
+                                                             h->dev);
                 launch_converge(h, G, false, st);
                 bool dotted = false;
                 z = vcycle<double>(c, 0, h->r, h->r, &dotted);
                 if (!dotted) k_pg_rz<<<G, kBlock, 0, st>>>(n, S, h->r, z, h->partials, h->dev);
                 launch_finalize<1>(h->partials, G, h->dev, EpiBeta{}, st);
-                if (nt) k_pg_p<true><<<G, kBlock, 0, st>>>(n, S, z, h->p, h->dev);
-                else k_pg_p<false><<<G, kBlock, 0, st>>>(n, S, z, h->p, h->dev);
+                if (nt) k_pg_p<true><<<G, kBlock, 0, st>>>(n, S, x, z, h->p, h->dev);
+                else k_pg_p<false><<<G, kBlock, 0, st>>>(n, S, x, z, h->p, h->dev);
             }
             HIP_CHECK(hipGetLastError());
             read_scalars(h, st);
             if (hs.done != kRunning) break;
         }
+        // the stopping iteration's x += alpha p (none when alpha itself failed)
+        k_pg_x_pending<<<G, kBlock, 0, st>>>(n, S, x, h->p, h->dev);
         if (hs.done == kFailed) {
             status = hs.status;
             break;

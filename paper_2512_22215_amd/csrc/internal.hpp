@@ -115,7 +115,8 @@ struct DevScalars {
     double inner_now;           // mixed: current inner tolerance
     double mean;                // coarsest: rhs mean
     int iters, max_iter, done, status;
-    int inner_iters, inner_max, inner_done, pad_;
+    int inner_iters, inner_max, inner_done;
+    int x_pending;              // CG + V-cycle: the iteration's x += alpha p is still due
     unsigned int ticket;        // grid reduction arrival counter (always 0 between kernels)
     unsigned int pad2_;
 };

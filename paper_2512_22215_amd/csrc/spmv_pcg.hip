@@ -235,6 +235,7 @@ struct EpiAlpha {
             ds->done = kFailed;
         } else {
             ds->alpha = ds->rho / pq;
+            ds->x_pending = 1;
         }
     }
 };

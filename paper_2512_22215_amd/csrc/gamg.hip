@@ -2094,7 +2094,7 @@ struct EpiRho {
 
 // r -= alpha q; ||r||^2.  The iteration's x += alpha p waits for the
 // direction update, which reads p anyway (k_pg_p), or, when the solve stops
-// in between, for k_pg_x_pending: one read of p per iteration instead of two.
+// in between, for k_x_pending: one read of p per iteration instead of two.
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_pg_update(int32_t n, int64_t S, double *__restrict__ r, const double *__restrict__ q,
@@ -2114,19 +2114,6 @@ k_pg_update(int32_t n, int64_t S, double *__restrict__ r, const double *__restri
     block_partials<1>(acc, partials);
 }
 
-// x += alpha p when the stopped solve's last iteration still owes it (the
-// same expression k_pg_p applies)
-__global__ void __launch_bounds__(kBlock)
-k_pg_x_pending(int32_t n, int64_t S, double *__restrict__ x, const double *__restrict__ p,
-               const DevScalars *ds) {
-    if (!ds->x_pending) return;
-    const double alpha = ds->alpha;
-    const int lane = threadIdx.x & 63;
-    for_each_slice(S, [&](int64_t s) {
-        const int64_t i = s * kWave + lane;
-        if (i < n) x[i] = x[i] + alpha * p[i];
-    });
-}
 
 // rho' = r.z; beta = rho'/rho
 __global__ void __launch_bounds__(kBlock)
@@ -2229,7 +2216,7 @@ int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, b
             if (hs.done != kRunning) break;
         }
         // the stopping iteration's x += alpha p (none when alpha itself failed)
-        k_pg_x_pending<<<G, kBlock, 0, st>>>(n, S, x, h->p, h->dev);
+        launch_x_pending(h, x, n, S, G, st);
         if (hs.done == kFailed) {
             status = hs.status;
             break;

@@ -348,8 +348,10 @@ void launch_residual_plain(ldu_t *h, const SellView<double> &A, const double *b,
 void launch_pcg_q(ldu_t *h, const SellView<double> &A, const double *p, double *q, int grid,
                   hipStream_t st);
 void set_done(ldu_t *h, int done, hipStream_t st);
-// epilogue after an x, r update whose partials hold ||r||^2 (and r.z)
+// epilogue after an r update whose partials hold ||r||^2 (and r.z)
 void launch_converge(ldu_t *h, int grid, bool with_beta, hipStream_t st);
+// x += alpha p (p: the handle's direction) if a stopped CG still owes it
+void launch_x_pending(ldu_t *h, double *x, int32_t n, int64_t S, int grid, hipStream_t st);
 
 // gamg.hip
 void gamg_build(ldu_t *h, const ldu_gamg_opts &o, hipStream_t st);

@@ -145,6 +145,7 @@ struct EpiResidual {
         ds->bnorm = sqrt(t[1]);
         ds->maxabs = t[3];
         if (has_p) ds->rho = t[2];
+        ds->x_pending = 0;  // a (re)start owes no solution update
         // b = 0 gives 0; a non-finite b or x gives a non-finite residual
         // (a NaN norm of b must not read as b = 0)
         const double res = ds->bnorm == 0.0 ? 0.0 : sqrt(t[0]) / ds->bnorm;
@@ -249,12 +250,15 @@ void launch_pcg_q(ldu_t *h, const SellView<double> &A, const double *p, double *
     launch_finalize<1>(h->partials, grid, h->dev, EpiAlpha{}, st);
 }
 
-// x += alpha p; r -= alpha q; ||r||^2 and r.D^-1 r
+// r -= alpha q; ||r||^2 and r.D^-1 r.  The iteration's x += alpha p waits
+// for the direction update, which reads p anyway (k_pcg_p), or, when the
+// solve stops in between, for k_x_pending: one read of p per iteration
+// instead of two.
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restrict__ x,
-             double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ q,
-             int precond, double *partials, const DevScalars *ds) {
+k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restrict__ r,
+             const double *__restrict__ q, int precond, double *partials,
+             const DevScalars *ds) {
     if (ds->done) return;
     const double alpha = ds->alpha;
     const int lane = threadIdx.x & 63;
@@ -262,9 +266,7 @@ k_pcg_update(int32_t n, int64_t S, const double *__restrict__ D, double *__restr
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
         if (i < n) {
-            const double xi = vld<NT>(x + i) + alpha * vld<NT>(p + i);
             const double ri = vld<NT>(r + i) - alpha * vld<NT>(q + i);
-            vst<NT>(x + i, xi);
             vst<NT>(r + i, ri);
             const double zi = precond ? ri / vld<NT>(D + i) : ri;
             acc[0] += ri * ri;
@@ -298,6 +300,7 @@ struct EpiConverge {
         } else if (with_beta) {
             ds->beta = t[1] / ds->rho;
             ds->rho = t[1];
+            ds->x_pending = 0;  // k_pcg_p applies it next
         }
     }
 };
@@ -307,22 +310,45 @@ void launch_converge(ldu_t *h, int grid, bool with_beta, hipStream_t st) {
     else launch_finalize<1>(h->partials, grid, h->dev, EpiConverge{h->hist, h->hist_cap, 0}, st);
 }
 
-// p = D^-1 r + beta p
+// x += alpha p (the iteration's solution update, deferred from
+// k_pcg_update); p = D^-1 r + beta p
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_pcg_p(int32_t n, int64_t S, const double *__restrict__ D, const double *__restrict__ r,
-        double *__restrict__ p, int precond, const DevScalars *ds) {
+        double *__restrict__ x, double *__restrict__ p, int precond, const DevScalars *ds) {
     if (ds->done) return;
-    const double beta = ds->beta;
+    const double alpha = ds->alpha, beta = ds->beta;
     const int lane = threadIdx.x & 63;
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
         if (i < n) {
+            const double pi = vld<NT>(p + i);
+            vst<NT>(x + i, vld<NT>(x + i) + alpha * pi);
             const double ri = vld<NT>(r + i);
             const double zi = precond ? ri / vld<NT>(D + i) : ri;
-            vst<NT>(p + i, zi + beta * vld<NT>(p + i));
+            vst<NT>(p + i, zi + beta * pi);
         }
     });
+}
+
+// x += alpha p when the stopped solve's last iteration still owes it: alpha
+// was formed (x_pending) but the direction update that applies it did not
+// run.  The same expression as in the direction updates.
+__global__ void __launch_bounds__(kBlock)
+k_x_pending(int32_t n, int64_t S, double *__restrict__ x, const double *__restrict__ p,
+            const DevScalars *ds) {
+    if (!ds->x_pending) return;
+    const double alpha = ds->alpha;
+    const int lane = threadIdx.x & 63;
+    for_each_slice(S, [&](int64_t s) {
+        const int64_t i = s * kWave + lane;
+        if (i < n) x[i] = x[i] + alpha * p[i];
+    });
+}
+
+void launch_x_pending(ldu_t *h, double *x, int32_t n, int64_t S, int grid, hipStream_t st) {
+    k_x_pending<<<grid, kBlock, 0, st>>>(n, S, x, h->p, h->dev);
+    HIP_CHECK(hipGetLastError());
 }
 
 __global__ void k_fill(double *a, int64_t n, double v) {
@@ -383,19 +409,25 @@ int pcg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, bool t
             for (int k = 0; k < every; ++k) {
                 launch_pcg_q(h, A, h->p, h->q, G, st);
                 if (nt)
-                    k_pcg_update<true><<<G, kBlock, 0, st>>>(n, S, A.diag, x, h->r, h->p, h->q,
-                                                             precond, h->partials, h->dev);
+                    k_pcg_update<true><<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->q, precond,
+                                                             h->partials, h->dev);
                 else
-                    k_pcg_update<false><<<G, kBlock, 0, st>>>(n, S, A.diag, x, h->r, h->p, h->q,
-                                                              precond, h->partials, h->dev);
+                    k_pcg_update<false><<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->q, precond,
+                                                              h->partials, h->dev);
                 launch_converge(h, G, true, st);
-                if (nt) k_pcg_p<true><<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->p, precond, h->dev);
-                else k_pcg_p<false><<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, h->p, precond, h->dev);
+                if (nt)
+                    k_pcg_p<true><<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, x, h->p, precond,
+                                                        h->dev);
+                else
+                    k_pcg_p<false><<<G, kBlock, 0, st>>>(n, S, A.diag, h->r, x, h->p, precond,
+                                                         h->dev);
             }
             HIP_CHECK(hipGetLastError());
             read_scalars(h, st);
             if (hs.done != kRunning) break;
         }
+        // the stopping iteration's x += alpha p (none when alpha itself failed)
+        launch_x_pending(h, x, n, S, G, st);
         if (hs.done == kFailed) {
             status = hs.status;
             break;

@@ -116,7 +116,7 @@ struct DevScalars {
     double mean;                // coarsest: rhs mean
     int iters, max_iter, done, status;
     int inner_iters, inner_max, inner_done;
-    int x_pending;              // CG + V-cycle: the iteration's x += alpha p is still due
+    int x_pending;              // CG: the iteration's x += alpha p is formed but not yet applied
     unsigned int ticket;        // grid reduction arrival counter (always 0 between kernels)
     unsigned int pad2_;
 };

@@ -2373,8 +2373,9 @@ int pcg_gamg_mixed(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, 
             for (int k = 0; k < every; ++k) {
                 launch_mx_q(h, A32, G, st);
                 launch_mx_update_plain(h, n, S, G, st);
-                z = vcycle<float>(c, 0, h->r32);
-                k_mxg_rz<<<G, kBlock, 0, st>>>(n, S, h->r32, z, h->partials, h->dev);
+                bool dotted = false;  // the last level-0 sweep may take r.z itself
+                z = vcycle<float>(c, 0, h->r32, h->r32, &dotted);
+                if (!dotted) k_mxg_rz<<<G, kBlock, 0, st>>>(n, S, h->r32, z, h->partials, h->dev);
                 launch_finalize<1>(h->partials, G, h->dev, EpiMxBeta{}, st);
                 k_mxg_p<<<G, kBlock, 0, st>>>(n, S, z, h->p32, h->dev);
             }

@@ -1,0 +1,105 @@
+"""Seeded random configurations of the GAMG path against the CPU oracle.
+
+Each configuration draws a box mesh (3 to 40 cells per side, at most about
+30,000 cells), a coefficient model (uniform or log-normal; symmetric or
+not), an optional random renumbering, and a cycle (pairwise or aggressive
+agglomeration from level 0, 1 or 2; damped Jacobi or two-stage Gauss-Seidel;
+diagonal or DIC coarsest; 1 or 2 sweeps; correction scaling on or off).  The
+draws come from numpy's default_rng with the configuration's index as seed,
+so every run checks the same configurations.  Bars, as in the fixed parity
+tests: aggregates integer-equal on every level, one V-cycle within 1e-11,
+standalone GAMG (forward, and transposed on non-symmetric matrices) and, on
+symmetric matrices, CG + V-cycle with equal iteration counts and solutions
+within 1e-9, and the mixed CG + V-cycle refined to 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from meshgen import box_case, random_order, relabel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+N_CONFIGS = 48
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def draw(seed):
+    """The configuration of one seed: the case and the cycle options."""
+    rng = np.random.default_rng(seed)
+    while True:
+        nx, ny, nz = (int(v) for v in rng.integers(3, 41, 3))
+        if nx * ny * nz <= 30000:
+            break
+    nonsym = float(rng.choice([0.0, 0.0, 0.5]))
+    coeff = str(rng.choice(["uniform", "lognormal"]))
+    c = box_case(nx, ny, nz, coeff=coeff, nonsym=nonsym, dirichlet_x0=1.0,
+                 seed=int(rng.integers(1 << 30)))
+    if rng.random() < 0.5:
+        c = relabel(c, random_order(c.n_cells, rng))
+    hier = {}
+    passes = int(rng.choice([1, 2, 3]))
+    if passes > 1:
+        hier = dict(passes=passes, aggressive_from=int(rng.integers(0, 3)))
+    cycle = dict(smoother=str(rng.choice(["jacobi", "jacobi", "gs2"])),
+                 coarsest=str(rng.choice(["diag", "dic"])))
+    if cycle["smoother"] == "gs2":
+        cycle["gs_inner"] = int(rng.integers(1, 3))
+    sweeps = int(rng.choice([1, 2]))
+    scale = int(rng.integers(0, 2))
+    return c, nonsym > 0, hier, cycle, sweeps, scale
+
+
+def describe(seed):
+    c, nonsym, hier, cycle, sweeps, scale = draw(seed)
+    return (f"seed {seed}: {c.n_cells} cells, nonsym {nonsym}, {hier or 'pairwise'}, "
+            f"{cycle}, sweeps {sweeps}, scale {scale}")
+
+
+@pytest.mark.parametrize("seed", range(N_CONFIGS))
+def test_random_configuration(seed):
+    from paper_2512_22215_amd import LduMatrix
+    print(describe(seed), flush=True)
+    c, nonsym, hier, cycle, sweeps, scale = draw(seed)
+    A = O.Ldu.from_case(c)
+    g = O.Gamg(A, **hier, **cycle)
+    m = LduMatrix.from_case(c)
+    opts = dict(n_pre=sweeps, n_post=sweeps, scale_correction=scale, **hier, **cycle)
+    m.gamg_setup(**opts)
+    assert m.n_levels() == g.n_levels
+    for lev in range(g.n_levels - 1):
+        assert np.array_equal(m.level(lev)["agg"].cpu().numpy(), g.level(lev).agg), lev
+    r = np.random.default_rng(1000 + seed).standard_normal(c.n_cells)
+    e = m.vcycle(_t(r), **opts).cpu().numpy()
+    ref = g.vcycle(r, n_pre=sweeps, n_post=sweeps, scale=bool(scale))
+    assert np.linalg.norm(e - ref) <= 1e-11 * np.linalg.norm(ref)
+    b = c.rhs[0]
+    for tr in ((False, True) if nonsym else (False,)):
+        rs = g.solve(b, tol=1e-8, max_cycles=100, n_pre=sweeps, n_post=sweeps,
+                     scale=bool(scale), transpose=tr)
+        if tr:
+            x, st = m.adjoint(_t(b), solver="gamg", rel_tol=1e-8, max_cycles=100, **opts)
+        else:
+            x, st = m.gamg(_t(b), rel_tol=1e-8, max_cycles=100, **opts)
+        assert st.iterations == rs.iterations, (tr, st.iterations, rs.iterations)
+        assert st.converged == (rs.status == O.OK), tr
+        if st.converged:
+            assert np.linalg.norm(x.cpu().numpy() - rs.x) <= 1e-9 * np.linalg.norm(rs.x), tr
+    if not nonsym:
+        copts = dict(opts, scale_correction=0)
+        m.gamg_setup(**copts)
+        x, st = m.pcg(_t(b), precond=2, rel_tol=1e-8)
+        rp = g.pcg(b, tol=1e-8, n_pre=sweeps, n_post=sweeps)
+        assert st.converged and rp.status == O.OK
+        assert st.iterations == rp.iterations, (st.iterations, rp.iterations)
+        assert np.linalg.norm(x.cpu().numpy() - rp.x) <= 1e-9 * np.linalg.norm(rp.x)
+        xm, sm = m.pcg(_t(b), precond=2, rel_tol=1e-10, precision="mixed")
+        assert sm.converged
+        res = np.linalg.norm(b - O.amul(A, xm.cpu().numpy())) / np.linalg.norm(b)
+        assert res <= 1e-10, res
+    m.close()

@@ -103,3 +103,55 @@ def test_random_configuration(seed):
         res = np.linalg.norm(b - O.amul(A, xm.cpu().numpy())) / np.linalg.norm(b)
         assert res <= 1e-10, res
     m.close()
+
+
+def draw_mesh(seed):
+    """A random mesh of the product tests: box sizes 1 to 60 per side (at
+    most 60,000 cells), symmetric or not, renumbered or not."""
+    rng = np.random.default_rng(5000 + seed)
+    while True:
+        nx, ny, nz = (int(v) for v in rng.integers(1, 61, 3))
+        if nx * ny * nz <= 60000:
+            break
+    nonsym = float(rng.choice([0.0, 0.5]))
+    c = box_case(nx, ny, nz, coeff=str(rng.choice(["uniform", "lognormal"])), nonsym=nonsym,
+                 dirichlet_x0=1.0, seed=int(rng.integers(1 << 30)))
+    if rng.random() < 0.5:
+        c = relabel(c, random_order(c.n_cells, rng))
+    return c, nonsym > 0, rng
+
+
+@pytest.mark.parametrize("seed", range(N_CONFIGS))
+def test_random_products_and_krylov(seed):
+    """Amul, Tmul and the FP32 Amul bit-exact, the coefficient gradients
+    bit-exact given lambda and x, diagonal PCG (symmetric meshes: equal
+    counts, solutions within 1e-10) and PBiCG (non-symmetric meshes: counts
+    within one, solutions within 1e-8) on random meshes."""
+    from paper_2512_22215_amd import LduMatrix
+    c, nonsym, rng = draw_mesh(seed)
+    print(f"seed {seed}: {c.n_cells} cells, {c.n_faces} faces, nonsym {nonsym}", flush=True)
+    A = O.Ldu.from_case(c)
+    m = LduMatrix.from_case(c)
+    x = rng.standard_normal(c.n_cells)
+    assert np.array_equal(m.amul(_t(x)).cpu().numpy(), O.amul(A, x))
+    assert np.array_equal(m.tmul(_t(x)).cpu().numpy(), O.tmul(A, x))
+    x32 = x.astype(np.float32)
+    assert np.array_equal(m.amul_f32(_t(x32)).cpu().numpy(), O.amul_f32(A, x32))
+    lam = rng.standard_normal(c.n_cells)
+    gd, gu, gl = (t.cpu().numpy() for t in m.coeff_grad(_t(lam), _t(x)))
+    rd, ru, rl = O.coeff_grad(A, lam, x)
+    assert np.array_equal(gd, rd) and np.array_equal(gu, ru) and np.array_equal(gl, rl)
+    b = c.rhs[0]
+    if not nonsym:
+        xg, st = m.pcg(_t(b), precond=1, rel_tol=1e-10)
+        ref = O.pcg(A, b, tol=1e-10)
+        assert st.converged and ref.status == O.OK
+        assert st.iterations == ref.iterations, (st.iterations, ref.iterations)
+        assert np.linalg.norm(xg.cpu().numpy() - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    else:
+        xg, st = m.pbicg(_t(b), precond=1, rel_tol=1e-10)
+        ref = O.pbicg(A, b, tol=1e-10)
+        assert st.converged and ref.status == O.OK
+        assert abs(st.iterations - ref.iterations) <= 1, (st.iterations, ref.iterations)
+        assert np.linalg.norm(xg.cpu().numpy() - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+    m.close()

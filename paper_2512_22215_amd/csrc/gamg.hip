@@ -2146,9 +2146,9 @@ struct EpiBeta {
 // x += alpha p (the iteration's solution update, deferred from k_pg_update);
 // p = z + beta p.  x and z are not read again before the next iteration's
 // direction update, so they stream past the caches (nontemporal) at every
-// size: the new p, which the CG product gathers next, then stays in the
-// Infinity Cache (the c3 CG product went from 133 to 122 us).
-template <bool NT>
+// size, while p keeps the default policy at every size: the new p, which the
+// CG product gathers next, then stays in the Infinity Cache (the c3 CG
+// product went from 133 to 122 us).
 __global__ void __launch_bounds__(kBlock)
 k_pg_p(int32_t n, int64_t S, double *__restrict__ x, const double *__restrict__ z,
        double *__restrict__ p, const DevScalars *ds) {
@@ -2158,9 +2158,9 @@ k_pg_p(int32_t n, int64_t S, double *__restrict__ x, const double *__restrict__ 
     for_each_slice(S, [&](int64_t s) {
         const int64_t i = s * kWave + lane;
         if (i < n) {
-            const double pi = vld<NT>(p + i);
+            const double pi = p[i];
             vst<true>(x + i, vld<true>(x + i) + alpha * pi);
-            vst<NT>(p + i, vld<true>(z + i) + beta * pi);
+            p[i] = vld<true>(z + i) + beta * pi;
         }
     });
 }
@@ -2216,8 +2216,7 @@ int pcg_gamg_fp64(ldu_t *h, const double *b, double *x, const ldu_pcg_opts &o, b
                 z = vcycle<double>(c, 0, h->r, h->r, &dotted);
                 if (!dotted) k_pg_rz<<<G, kBlock, 0, st>>>(n, S, h->r, z, h->partials, h->dev);
                 launch_finalize<1>(h->partials, G, h->dev, EpiBeta{}, st);
-                if (nt) k_pg_p<true><<<G, kBlock, 0, st>>>(n, S, x, z, h->p, h->dev);
-                else k_pg_p<false><<<G, kBlock, 0, st>>>(n, S, x, z, h->p, h->dev);
+                k_pg_p<<<G, kBlock, 0, st>>>(n, S, x, z, h->p, h->dev);
             }
             HIP_CHECK(hipGetLastError());
             read_scalars(h, st);

@@ -242,6 +242,14 @@ int gamg_level_export(ldu_handle h, int level, int32_t *agg, int32_t *owner,
  * 0 when every slot reads 32-bit columns.  Either way the products are the
  * same bit for bit. */
 int ldu_level_layout(ldu_handle h, int level, int *compressed, int *col16);
+/* The form of level l's one-pass down leg, r_c = P^T (I - omega A D^-1) r,
+ * which cycles with one Jacobi pre-sweep from zero and no correction scaling
+ * use (HOST outputs, lanes may be NULL): 0 not built (the coarsest level, or
+ * no such cycle has run on this hierarchy); 1 the operator R in compressed
+ * slices; 2 R in CSR, with *lanes lanes per row; 3 a product over the
+ * level's own slices with stored values -omega a_ij / D_j, then the member
+ * sums.  LDU_ERR_STATE without a hierarchy, LDU_ERR_ARG for a bad level. */
+int ldu_level_downleg(ldu_handle h, int level, int *form, int *lanes);
 
 /* Adjoint solve A^T lambda = g on the transposed coefficients (upper and
  * lower exchanged on every level) with solver 0: PCG (opts is an

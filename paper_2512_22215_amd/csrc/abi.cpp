@@ -421,6 +421,25 @@ int ldu_level_layout(ldu_handle h, int level, int *compressed, int *col16) {
     return LDU_OK;
 }
 
+int ldu_level_downleg(ldu_handle h, int level, int *form, int *lanes) {
+    if (!h) return fail(LDU_ERR_ARG, "NULL handle");
+    if (!h->gamg_ready) return fail(LDU_ERR_STATE, "GAMG hierarchy not set up");
+    if (level < 0 || level >= (int)h->levels.size()) return fail(LDU_ERR_ARG, "bad level");
+    const Level &L = h->levels[level];
+    int f = 0, g = 0;
+    if (L.ah) {
+        f = 3;
+    } else if (L.R.sptr) {
+        f = 1;
+    } else if (L.Rc.rptr) {
+        f = 2;
+        g = L.Rc.group;
+    }
+    if (form) *form = f;
+    if (lanes) *lanes = g;
+    return LDU_OK;
+}
+
 int gamg_level_export(ldu_handle h, int level, int32_t *agg, int32_t *owner, int32_t *neighbour,
                       double *diag, double *upper, double *lower, void *hip_stream) {
     if (!h) return fail(LDU_ERR_ARG, "NULL handle");

@@ -26,7 +26,8 @@ EXPORTED = (
     "ldu_destroy", "ldu_amul", "ldu_tmul", "ldu_amul_f32", "ldu_residual", "pcg_solve",
     "pcg_solve_noalloc",
     "pbicg_solve", "gamg_setup", "gamg_solve", "gamg_vcycle", "gamg_level_size", "gamg_level_export",
-    "ldu_level_layout", "ldu_adjoint_solve", "ldu_coeff_grad", "ldu_assemble_pressure", "ldu_last_error",
+    "ldu_level_layout", "ldu_level_downleg", "ldu_adjoint_solve", "ldu_coeff_grad",
+    "ldu_assemble_pressure", "ldu_last_error",
 )
 
 
@@ -109,6 +110,7 @@ def lib():
     L.gamg_level_size.argtypes = [vp, i, C.POINTER(i64), C.POINTER(i64)]
     L.gamg_level_export.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp]
     L.ldu_level_layout.argtypes = [vp, i, C.POINTER(i), C.POINTER(i)]
+    L.ldu_level_downleg.argtypes = [vp, i, C.POINTER(i), C.POINTER(i)]
     L.ldu_adjoint_solve.argtypes = [vp, vp, vp, i, vp, C.POINTER(Stats), vp]
     L.ldu_coeff_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.ldu_assemble_pressure.argtypes = [vp] * 13
@@ -329,6 +331,14 @@ class LduMatrix:
         cmp_, c16 = C.c_int(), C.c_int()
         _check(lib().ldu_level_layout(self._h, l, C.byref(cmp_), C.byref(c16)), False)
         return {"compressed": bool(cmp_.value), "col16": bool(c16.value)}
+
+    def downleg(self, l):
+        """Form of level l's one-pass down leg: ("none" | "r_compressed" |
+        "r_csr" | "scaled_slices", lanes per row of a CSR R)."""
+        form, lanes = C.c_int(), C.c_int()
+        _check(lib().ldu_level_downleg(self._h, l, C.byref(form), C.byref(lanes)), False)
+        names = {0: "none", 1: "r_compressed", 2: "r_csr", 3: "scaled_slices"}
+        return names[form.value], lanes.value
 
     def adjoint(self, g, use_gamg=False, x0=None, history=0, solver=None, **kw):
         """A^T lambda = g; solver "pcg" (default), "gamg" (or use_gamg=True) or

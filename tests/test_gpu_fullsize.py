@@ -144,6 +144,12 @@ def test_c3_aggressive_hierarchy_fp64_and_mixed(c3):
                     ("upper", r2.upper), ("lower", r2.lower)):
         assert np.array_equal(l2[key].cpu().numpy(), rv), key
     del g
+    # the down legs the headline runs: level 0 over its own scaled slices,
+    # level 1 (395,067 coarse rows) through R in compressed slices, the rest
+    # through R in CSR
+    forms = [m.downleg(k)[0] for k in range(m.n_levels() - 1)]
+    assert forms[0] == "scaled_slices" and forms[1] == "r_compressed", forms
+    assert all(f == "r_csr" for f in forms[2:]), forms
     b = c3.rhs[0]
     x64, s64 = m.pcg(_t(b), precond=2, rel_tol=1e-8, history=1000)
     xm, sm = m.pcg(_t(b), precond=2, rel_tol=1e-8, precision="mixed")

@@ -54,6 +54,29 @@ def hist_close(h, ref, rel=1e-9):
     return h.shape == ref.shape and bool(np.all(np.abs(h - ref) <= rel * ref + 1e-15))
 
 
+def expected_downleg(g, level, plain):
+    """The one-pass down leg the library builds for level `level` of the
+    oracle hierarchy g: a plain-slice level above 300,000 coarse rows runs
+    over its own scaled slices; otherwise R, in compressed slices above
+    300,000 rows, else in CSR with G lanes per row, G the power of two
+    nearest (entries per row) / 2, from 1 to 16 (R's entries: the union of
+    the members' columns and their diagonals, counted here with scipy)."""
+    import scipy.sparse as sp
+    L, C = g.level(level), g.level(level + 1)
+    if C.n > 300000:
+        return ("scaled_slices", 0) if plain else ("r_compressed", 0)
+    rows = np.concatenate([L.owner, L.neighbour, np.arange(L.n)])
+    cols = np.concatenate([L.neighbour, L.owner, np.arange(L.n)])
+    M = sp.csr_matrix((np.ones(rows.size), (rows, cols)), shape=(L.n, L.n))
+    P = sp.csr_matrix((np.ones(L.n), (np.arange(L.n), L.agg)), shape=(L.n, C.n))
+    nnz = (P.T @ M).tocsr().nnz
+    per = nnz / C.n / 2
+    lanes = 1
+    while lanes < 16 and 2.0 * lanes <= per * 1.41421356:
+        lanes *= 2
+    return "r_csr", lanes
+
+
 def true_res(c, x):
     A = O.Ldu.from_case(c)
     b = c.rhs[0]
@@ -469,6 +492,12 @@ def test_csr_restriction_lane_groups(name):
     assert st.converged and st.iterations == ref.iterations
     assert hist_close(st.history, ref.history, 1e-8)
     assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    # the forms the solve ran: R in CSR on every level, with the lanes per row
+    # the library's rule gives (over the four cases: 2, 4, 8 and 16)
+    forms = [m.downleg(lev) for lev in range(g.n_levels - 1)]
+    print(name, forms)
+    for lev, f in enumerate(forms):
+        assert f == expected_downleg(g, lev, m.layout(lev)["compressed"] is False), (lev, f)
     xt, stt = m.adjoint(_t(b), solver="pcg", precond=2, rel_tol=1e-8)
     reft = g.pcg(b, tol=1e-8, n_pre=1, n_post=1, transpose=True)
     assert stt.converged and stt.iterations == reft.iterations
@@ -501,6 +530,9 @@ def test_scaled_slice_down_leg(hier):
     # level above the 300,000 rows up to which R is stored in CSR
     assert m.layout(0)["compressed"] is False and m.layout(0)["col16"] is True
     assert g.level(1).n > 300000
+    assert m.downleg(0) == ("scaled_slices", 0)
+    for lev in range(1, g.n_levels - 1):
+        assert m.downleg(lev) == expected_downleg(g, lev, m.layout(lev)["compressed"] is False)
     r = np.random.default_rng(43).standard_normal(c.n_cells)
     # (the agglomeration settings go with every call: a call whose settings
     # differ from the cached hierarchy's builds a new one)
@@ -546,6 +578,7 @@ def test_scaled_slice_down_leg_nonsymmetric(hier):
     m.gamg_setup(**ONE_SWEEP, **hier)
     g = O.Gamg(A, **hier)
     assert m.layout(0)["compressed"] is False and g.level(1).n > 300000
+    assert m.downleg(0) == ("scaled_slices", 0)
     r = np.random.default_rng(45).standard_normal(c.n_cells)
     e = m.vcycle(_t(r), **ONE_SWEEP, **hier).cpu().numpy()
     ref = g.vcycle(r, n_pre=1, n_post=1, scale=False)

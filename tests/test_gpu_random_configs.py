@@ -155,3 +155,54 @@ def test_random_products_and_krylov(seed):
         assert abs(st.iterations - ref.iterations) <= 1, (st.iterations, ref.iterations)
         assert np.linalg.norm(xg.cpu().numpy() - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
     m.close()
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_differentiable_solve(seed):
+    """The differentiable solve on random small meshes (at most 400 cells,
+    symmetric or not, renumbered or not): x and the gradients of
+    L = 0.5 |x - x_t|^2 with respect to diag, upper, lower and b through the
+    autograd Function, against dense float64 algebra on the CPU
+    (x = A^-1 b; lambda = A^-T (x - x_t); dL/db = lambda; dL/dA = -lambda x^T
+    read at the diagonal and at each face's two entries), for the CG + V-cycle
+    in FP64 and in the mixed form (symmetric meshes) and PBiCG in FP64
+    (non-symmetric meshes; PBiCG has no mixed form)."""
+    from paper_2512_22215_amd import LduMatrix, ldu_solve
+    rng = np.random.default_rng(9000 + seed)
+    while True:
+        nx, ny, nz = (int(v) for v in rng.integers(1, 12, 3))
+        if 2 <= nx * ny * nz <= 400:
+            break
+    nonsym = bool(rng.random() < 0.5)
+    c = box_case(nx, ny, nz, coeff="lognormal", nonsym=0.5 if nonsym else 0.0,
+                 dirichlet_x0=1.0, seed=int(rng.integers(1 << 30)))
+    if rng.random() < 0.5:
+        c = relabel(c, random_order(c.n_cells, rng))
+    n, own, nb = c.n_cells, c.owner, c.neighbour
+    A = np.diag(c.diag.astype(np.float64))
+    A[own, nb] = c.upper
+    A[nb, own] = c.lower
+    b = c.rhs[0]
+    xt = rng.standard_normal(n)
+    x_ref = np.linalg.solve(A, b)
+    lam = np.linalg.solve(A.T, x_ref - xt)
+    gA = -np.outer(lam, x_ref)
+    ref = {"diag": np.diag(gA), "upper": gA[own, nb], "lower": gA[nb, own], "b": lam}
+    m = LduMatrix.from_case(c)
+    method = "pbicg" if nonsym else "pcg"
+    for prec in (("fp64",) if nonsym else ("fp64", "mixed")):
+        opts = dict(rel_tol=1e-13, precision=prec)
+        if method == "pcg":
+            opts["precond"] = 2
+        leaves = {k: _t(v).requires_grad_() for k, v in
+                  (("diag", c.diag), ("upper", c.upper), ("lower", c.lower), ("b", b))}
+        x = ldu_solve(leaves["diag"], leaves["upper"], leaves["lower"], leaves["b"], m,
+                      method, **opts)
+        loss = 0.5 * ((x - _t(xt)) ** 2).sum()
+        loss.backward()
+        xg = x.detach().cpu().numpy()
+        assert np.linalg.norm(xg - x_ref) <= 1e-10 * np.linalg.norm(x_ref), prec
+        for k, v in ref.items():
+            got = leaves[k].grad.cpu().numpy()
+            assert np.linalg.norm(got - v) <= 1e-9 * np.linalg.norm(v), (prec, k)
+    m.close()

@@ -27,7 +27,7 @@ def build(verbose: bool = False) -> str:
            "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", tmp] + sources()
+           "-o", tmp] + sources() + ["-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)

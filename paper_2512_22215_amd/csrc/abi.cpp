@@ -8,6 +8,8 @@
 #include <new>
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "internal.hpp"
 
 namespace ldu {
@@ -79,6 +81,15 @@ int guarded(ldu_t *h, F &&f) {
 }
 
 hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// a roctx range around one ABI call: `rocprofv3 --marker-trace` shows the
+// setup, solve and gradient calls on the timeline beside their kernels
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 void check_pcg_opts(const ldu_pcg_opts &o) {
     if (!(o.rel_tol >= 0.0) || o.abs_tol != 0.0 || o.max_iter < 0 || o.check_every < 1 ||
@@ -158,6 +169,7 @@ const char *ldu_last_error(void) { return g_last_error.c_str(); }
 int ldu_create(int32_t nCells, int64_t nFaces, const int32_t *owner, const int32_t *neighbour,
                const double *diag, const double *upper, const double *lower, void *hip_stream,
                ldu_handle *out) {
+    Range range("ldu_create");
     if (!out) return fail(LDU_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (nCells < 1 || nFaces < 0) return fail(LDU_ERR_ARG, "nCells must be >= 1, nFaces >= 0");
@@ -223,6 +235,7 @@ int ldu_destroy(ldu_handle h) {
 
 int ldu_set_coeffs(ldu_handle h, const double *diag, const double *upper, const double *lower,
                    void *hip_stream) {
+    Range range("ldu_set_coeffs");
     if (!h) return fail(LDU_ERR_ARG, "NULL handle");
     if (!diag || (h->L0.nf > 0 && (!upper || !lower))) return fail(LDU_ERR_ARG, "NULL array");
     return guarded(h, [&] {
@@ -252,6 +265,7 @@ int ldu_assemble_pressure(ldu_handle h, const double *gamma, const double *weigh
                           const double *mag_sf, const double *delta, const double *diag_bc,
                           const double *phi, const double *b_bc, double *b, double *diag,
                           double *upper, double *lower, void *hip_stream) {
+    Range range("ldu_assemble_pressure");
     if (!h) return fail(LDU_ERR_ARG, "NULL handle");
     if (!gamma || (h->L0.nf > 0 && (!weights || !mag_sf || !delta || (b && !phi))) ||
         (phi && !b))
@@ -336,11 +350,13 @@ static int pcg_common(ldu_handle h, const double *b, double *x, const ldu_pcg_op
 
 int pcg_solve(ldu_handle h, const double *b, double *x, const ldu_pcg_opts *opts,
               ldu_stats *stats, void *hip_stream) {
+    Range range("pcg_solve");
     return pcg_common(h, b, x, opts, stats, hip_stream, false);
 }
 
 int pcg_solve_noalloc(ldu_handle h, const double *b, double *x, const ldu_pcg_opts *opts,
                       ldu_stats *stats, void *hip_stream) {
+    Range range("pcg_solve_noalloc");
     if (!h || !b || !x) return fail(LDU_ERR_ARG, "NULL argument");
     return guarded(h, [&] {
         ldu_pcg_opts o;
@@ -355,6 +371,7 @@ int pcg_solve_noalloc(ldu_handle h, const double *b, double *x, const ldu_pcg_op
 }
 
 int gamg_setup(ldu_handle h, const ldu_gamg_opts *opts, void *hip_stream) {
+    Range range("gamg_setup");
     if (!h) return fail(LDU_ERR_ARG, "NULL handle");
     return guarded(h, [&] {
         ldu_gamg_opts o;
@@ -383,11 +400,13 @@ static int gamg_common(ldu_handle h, const double *b, double *x, const ldu_gamg_
 
 int gamg_solve(ldu_handle h, const double *b, double *x, const ldu_gamg_opts *opts,
                ldu_stats *stats, void *hip_stream) {
+    Range range("gamg_solve");
     return gamg_common(h, b, x, opts, stats, hip_stream, false);
 }
 
 int gamg_vcycle(ldu_handle h, const double *r, double *e, const ldu_gamg_opts *opts,
                 void *hip_stream) {
+    Range range("gamg_vcycle");
     if (!h || !r || !e) return fail(LDU_ERR_ARG, "NULL argument");
     return guarded(h, [&] {
         ldu_gamg_opts o;
@@ -475,11 +494,13 @@ static int pbicg_common(ldu_handle h, const double *b, double *x, const ldu_pcg_
 
 int pbicg_solve(ldu_handle h, const double *b, double *x, const ldu_pcg_opts *opts,
                 ldu_stats *stats, void *hip_stream) {
+    Range range("pbicg_solve");
     return pbicg_common(h, b, x, opts, stats, hip_stream, false);
 }
 
 int ldu_adjoint_solve(ldu_handle h, const double *g, double *lambda, int solver,
                       const void *opts, ldu_stats *stats, void *hip_stream) {
+    Range range("ldu_adjoint_solve");
     switch (solver) {
     case LDU_SOLVER_PCG:
         return pcg_common(h, g, lambda, static_cast<const ldu_pcg_opts *>(opts), stats,
@@ -497,6 +518,7 @@ int ldu_adjoint_solve(ldu_handle h, const double *g, double *lambda, int solver,
 
 int ldu_coeff_grad(ldu_handle h, const double *lambda, const double *x, double *g_diag,
                    double *g_upper, double *g_lower, void *hip_stream) {
+    Range range("ldu_coeff_grad");
     if (!h || !lambda || !x) return fail(LDU_ERR_ARG, "NULL argument");
     return guarded(h, [&] {
         launch_coeff_grad(h->L0, lambda, x, g_diag, g_upper, g_lower, S(hip_stream));

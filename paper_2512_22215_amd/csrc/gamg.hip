@@ -1096,6 +1096,14 @@ static bool rop_cycle(const ldu_gamg_opts &o) {
     return o.smoother == LDU_SMOOTH_JACOBI && o.n_pre == 1 && !o.scale_correction;
 }
 
+// entries a lane of the compressed-slice R product loads before its gathers:
+// R's rows are longer than the level's own (47 entries on the c3 headline's
+// level 1), so it takes larger batches than kCmpBatch (FP64 solves with 24,
+// 32 and 48 entries: 147.2, 146.0 and 148.0 ms; mixed ones: 116.4, 115.5
+// and 114.3 ms)
+template <typename T>
+constexpr int kRBatch = sizeof(T) == 8 ? 32 : 48;
+
 // r_c = R r (row c: columns ascending, from zero), and the coarse level's
 // first Jacobi sweep from zero e_c = omega r_c / D_c when ec_first is given
 template <typename T>
@@ -1112,8 +1120,8 @@ k_vc_rrestrict_cmp(SellView<T> R, const T *__restrict__ r, T *__restrict__ rc,
             // trip overlaps the row's gathers
             const T dc = ec_first ? Dc[c] : T(1);
             T acc = T(0);
-            cmp_entries_at<kCmpBatch>(R, hd.b0, hd.w, lane, Direct<T>{r},
-                                      [&](int32_t, T v, T xv) { acc = acc + v * xv; });
+            cmp_entries_at<kRBatch<T>>(R, hd.b0, hd.w, lane, Direct<T>{r},
+                                       [&](int32_t, T v, T xv) { acc = acc + v * xv; });
             rc[c] = acc;
             if (ec_first) ec_first[c] = omega * acc / dc;
         }

@@ -197,6 +197,35 @@ def test_pcg_edge_cases():
     assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
 
 
+@pytest.mark.parametrize("k", [1, 2, 15, 16, 17, 33])
+def test_iteration_cap_keeps_the_last_update(k):
+    """A solve stopped by its iteration cap, inside or at the end of a
+    16-iteration check block, has applied its last iteration's x += alpha p,
+    which the CG loops defer to the direction update: after k iterations x
+    equals the oracle's, for diagonal PCG and for CG + V-cycle (one sweep,
+    three matching passes below level 1), forward and transposed (the matrix
+    is symmetric, so both match the oracle's forward solve)."""
+    c = _gamg_case("c3s")
+    A = O.Ldu.from_case(c)
+    b = c.rhs[0]
+    m = _lib().from_case(c)
+    x, st = m.pcg(_t(b), rel_tol=1e-14, max_iter=k)
+    ref = O.pcg(A, b, tol=1e-14, max_iter=k)
+    print(f"k={k} diag: it {st.iterations} status {st.status}", flush=True)
+    assert st.iterations == k == ref.iterations and st.status == 1
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+    hier = dict(passes=3, aggressive_from=1)
+    m.gamg_setup(n_pre=1, n_post=1, **hier)
+    rp = O.Gamg(A, **hier).pcg(b, tol=1e-14, max_iter=k, n_pre=1, n_post=1)
+    for name, (xp, sp) in (("forward", m.pcg(_t(b), precond=2, rel_tol=1e-14, max_iter=k)),
+                           ("transposed", m.adjoint(_t(b), solver="pcg", precond=2,
+                                                    rel_tol=1e-14, max_iter=k))):
+        print(f"k={k} cg+vcycle {name}: it {sp.iterations} status {sp.status}", flush=True)
+        assert sp.iterations == k == rp.iterations and sp.status == 1, name
+        assert np.linalg.norm(xp.cpu().numpy() - rp.x) <= 1e-10 * np.linalg.norm(rp.x), name
+    m.close()
+
+
 def _gamg_case(name):
     if name == "c2s":
         return config_case("c2", n=24)

@@ -226,6 +226,41 @@ def test_iteration_cap_keeps_the_last_update(k):
     m.close()
 
 
+def test_warm_start_matches_oracle():
+    """Solvers started from a seeded nonzero x0 (the time loop's warm start):
+    iteration counts equal the oracle's from the same x0, and the solutions
+    agree: diagonal PCG and CG + V-cycle to 1e-8, the transposed CG + V-cycle
+    (the matrix is symmetric), and 30 cycles of standalone GAMG."""
+    c = _gamg_case("c3s")
+    A = O.Ldu.from_case(c)
+    b = c.rhs[0]
+    x0 = np.random.default_rng(77).standard_normal(c.n_cells)
+    m = _lib().from_case(c)
+    hier = dict(passes=3, aggressive_from=1)
+    m.gamg_setup(n_pre=1, n_post=1, **hier)
+    g = O.Gamg(A, **hier)
+    runs = [
+        ("pcg", m.pcg(_t(b), x0=_t(x0), rel_tol=1e-8), O.pcg(A, b, x0=x0, tol=1e-8), 1e-9),
+        ("pcg+vcycle", m.pcg(_t(b), x0=_t(x0), precond=2, rel_tol=1e-8),
+         g.pcg(b, x0=x0, tol=1e-8, n_pre=1, n_post=1), 1e-9),
+        ("adjoint pcg+vcycle", m.adjoint(_t(b), x0=_t(x0), solver="pcg", precond=2,
+                                         rel_tol=1e-8),
+         g.pcg(b, x0=x0, tol=1e-8, n_pre=1, n_post=1), 1e-9),
+        # standalone GAMG converges slowly on this graded box: 30 cycles
+        ("gamg", m.gamg(_t(b), x0=_t(x0), rel_tol=1e-14, n_pre=1, n_post=1, max_cycles=30,
+                        **hier),
+         g.solve(b, x0=x0, tol=1e-14, n_pre=1, n_post=1, max_cycles=30), 1e-10),
+    ]
+    for name, (x, st), ref, tol in runs:
+        print(f"{name}: it {st.iterations} oracle {ref.iterations} "
+              f"residual {st.final_residual:.3e}", flush=True)
+        assert st.iterations == ref.iterations, name
+        assert st.converged == (ref.status == 0), name
+        xr = ref.x
+        assert np.linalg.norm(x.cpu().numpy() - xr) <= tol * np.linalg.norm(xr), name
+    m.close()
+
+
 def _gamg_case(name):
     if name == "c2s":
         return config_case("c2", n=24)

@@ -230,7 +230,8 @@ def test_warm_start_matches_oracle():
     """Solvers started from a seeded nonzero x0 (the time loop's warm start):
     iteration counts equal the oracle's from the same x0, and the solutions
     agree: diagonal PCG and CG + V-cycle to 1e-8, the transposed CG + V-cycle
-    (the matrix is symmetric), and 30 cycles of standalone GAMG."""
+    (the matrix is symmetric), 30 cycles of standalone GAMG, and the mixed
+    form refined to 1e-12 against the FP64 oracle."""
     c = _gamg_case("c3s")
     A = O.Ldu.from_case(c)
     b = c.rhs[0]
@@ -258,6 +259,14 @@ def test_warm_start_matches_oracle():
         assert st.converged == (ref.status == 0), name
         xr = ref.x
         assert np.linalg.norm(x.cpu().numpy() - xr) <= tol * np.linalg.norm(xr), name
+    # the mixed form from the same x0, refined to 1e-12, against the FP64 oracle
+    xm, sm = m.pcg(_t(b), x0=_t(x0), precond=2, rel_tol=1e-12, precision="mixed")
+    rf = g.pcg(b, x0=x0, tol=1e-12, n_pre=1, n_post=1)
+    print(f"mixed: refinements {sm.refinements} inner {sm.iterations}", flush=True)
+    assert sm.converged and true_res(c, xm.cpu().numpy()) <= 1e-12
+    err = np.linalg.norm(xm.cpu().numpy() - rf.x) / np.linalg.norm(rf.x)
+    print(f"mixed vs FP64 oracle: {err:.2e}", flush=True)
+    assert err <= 1e-10
     m.close()
 
 

@@ -512,6 +512,56 @@ def test_deterministic_bitwise():
     assert torch.equal(p1, p2)
 
 
+def test_interleaved_handles_and_a_side_stream():
+    """Two matrices of different sizes, each with its own hierarchy, solved in
+    alternation (CG + V-cycle in FP64 and mixed, the adjoint), give bitwise
+    the results each gives alone; so does a solve on a side stream (the
+    binding passes torch's current stream), and closing one handle leaves
+    the other working."""
+    ca, cb = _gamg_case("c3s"), CASES["ragged"]
+    hier = dict(n_pre=1, n_post=1, passes=3, aggressive_from=1)
+
+    def runs(m, c):
+        b = _t(c.rhs[0])
+        return [m.pcg(b, precond=2, rel_tol=1e-8)[0],
+                m.pcg(b, precond=2, rel_tol=1e-10, precision="mixed")[0],
+                m.adjoint(b, solver="pcg", precond=2, rel_tol=1e-8)[0]]
+
+    ma = _lib().from_case(ca)
+    ma.gamg_setup(**hier)
+    alone_a = runs(ma, ca)
+    ma.close()
+    mb = _lib().from_case(cb)
+    mb.gamg_setup(**hier)
+    alone_b = runs(mb, cb)
+    mb.close()
+    ma, mb = _lib().from_case(ca), _lib().from_case(cb)
+    ma.gamg_setup(**hier)
+    mb.gamg_setup(**hier)
+    ba, bb = _t(ca.rhs[0]), _t(cb.rhs[0])
+    got_a, got_b = [], []
+    for k, (fa, fb) in enumerate(((lambda: ma.pcg(ba, precond=2, rel_tol=1e-8),
+                                   lambda: mb.pcg(bb, precond=2, rel_tol=1e-8)),
+                                  (lambda: ma.pcg(ba, precond=2, rel_tol=1e-10, precision="mixed"),
+                                   lambda: mb.pcg(bb, precond=2, rel_tol=1e-10, precision="mixed")),
+                                  (lambda: ma.adjoint(ba, solver="pcg", precond=2, rel_tol=1e-8),
+                                   lambda: mb.adjoint(bb, solver="pcg", precond=2, rel_tol=1e-8)))):
+        got_a.append(fa()[0])
+        got_b.append(fb()[0])
+    for k in range(3):
+        assert torch.equal(got_a[k], alone_a[k]) and torch.equal(got_b[k], alone_b[k]), k
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        xs = mb.pcg(bb, precond=2, rel_tol=1e-8)[0]
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    assert torch.equal(xs, alone_b[0])
+    ma.close()
+    assert torch.equal(mb.pcg(bb, precond=2, rel_tol=1e-8)[0], alone_b[0])
+    mb.close()
+
+
 @pytest.mark.parametrize("name", ["c3p", "c2s", "ragged"])
 def test_pcg_gamg_matches_oracle(name):
     c = _gamg_case(name)
